@@ -1,0 +1,171 @@
+/*
+ * rqa.h -- C ABI of the MI355X (gfx950) library for the hot path of averaged
+ * recurrence quantification analysis (Panis, Adamek & Marwan, "Averaged
+ * Recurrence Quantification Analysis", arXiv 2208.09136).
+ *
+ * What the library computes, for a float32 series y[0..n-1]:
+ *   - delay vectors x(t) = [y(t), y(t-tau), ..., y(t-(m-1)tau)] (Methodology,
+ *     Lorenz-system subsection).  Vector i (0-based) has component k equal to
+ *     y[i + (m-1-k)tau]; there are nv = n - (m-1)tau vectors.
+ *   - a key per pair i < j: the maximum norm max_k |d_k| (Recurrence
+ *     quantification analysis section, after Eq. 1) or the squared Euclidean
+ *     norm, summed left to right over k = 0..m-1, every operation rounded to
+ *     binary32 and no fused multiply-add; d_k = y[i+(m-1-k)tau] -
+ *     y[j+(m-1-k)tau].  Euclidean thresholds are therefore in squared units.
+ *   - the recurrence matrix of Eq. 1 over the upper triangle j > i
+ *     (Technical implementation on a GPU), restricted to j - i >= theiler:
+ *     M = (nv-theiler)(nv-theiler+1)/2 pairs.  A pair recurs at threshold
+ *     eps iff key <= eps (equal to the paper's strict Heaviside at the next
+ *     float above eps).
+ *   - the threshold for a preselected recurrence rate RR (Averaged RQA
+ *     section): the k-th smallest key, k = ceil(RR * M) with RR quantised to
+ *     1e-9 and k clamped to [1, M].
+ *   - RR (Eq. 3) = C / M with C = #{key <= eps}, the diagonal-line
+ *     determinism DET (Eq. 4) = (points on diagonal lines of length >= lmin)
+ *     / C, and the averaged DET (the averaged-determinism equation of the
+ *     Averaged RQA section) = mean of DET over the given RR targets.  Lines
+ *     that touch the border of the plot count with their length inside it.
+ *
+ * Conventions for every call:
+ *   - All functions return rqa_status; nothing throws or aborts.  On an
+ *     error the outputs are left untouched and rqa_last_error() describes it.
+ *   - Series pointers are DEVICE pointers on the context's device; every
+ *     *_out pointer and every other array argument is HOST memory.  The
+ *     caller owns all of them; the library never keeps a pointer past a call.
+ *   - Calls are ordered on the context's stream and synchronise with it
+ *     before returning; outputs are complete on return.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - n must be < 2^31.  K (number of RR targets or thresholds) is 1..128.
+ */
+#ifndef RQA_H
+#define RQA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RQA_MAX_K 128
+
+typedef struct rqa_ctx rqa_ctx;
+
+typedef enum {
+    RQA_OK = 0,
+    RQA_ERR_INVALID_ARG = -1, /* null pointer, zero m/tau/theiler/lmin, K out of range, bad RR or eps, unknown norm/flag */
+    RQA_ERR_TOO_SHORT = -2,   /* nv <= theiler: there is no pair to evaluate */
+    RQA_ERR_NONFINITE = -3,   /* a NaN or infinite sample in the series */
+    RQA_ERR_DEVICE = -4,      /* a HIP runtime error; the text is in rqa_last_error() */
+    RQA_ERR_NOMEM = -5,       /* device scratch could not be allocated */
+    RQA_ERR_UNSUPPORTED = -6  /* a flag or shape the kernels do not implement */
+} rqa_status;
+
+typedef enum { RQA_NORM_MAX = 0, RQA_NORM_EUCLIDEAN = 1 } rqa_norm;
+
+/* Embedding dimension m >= 1, delay tau >= 1, norm (rqa_norm), Theiler window
+ * theiler >= 1 (pairs with j - i < theiler are excluded; 1 gives the paper's
+ * j > i), minimal line length lmin in 1..16 (the paper uses 2). */
+typedef struct {
+    uint32_t m;
+    uint32_t tau;
+    uint32_t norm;
+    uint32_t theiler;
+    uint32_t lmin;
+} rqa_params;
+
+/* flags */
+enum {
+    RQA_SEL_PLAIN = 0,   /* exact radix/histogram threshold selection */
+    RQA_SEL_LEARNED = 1, /* bracket from the loaded model, exact in-bracket resolution, plain fallback */
+    RQA_FULL_HIST = 2    /* reserved for the full line-length histogram: RQA_ERR_UNSUPPORTED */
+};
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t on
+ * that device to order all work on, or NULL for a stream the context creates
+ * and owns.  The context owns its device scratch (grown on demand, freed by
+ * rqa_destroy).  *out receives the context on RQA_OK. */
+rqa_status rqa_create(rqa_ctx **out, int device, void *hip_stream);
+
+/* Free a context and its scratch.  NULL is ignored. */
+void rqa_destroy(rqa_ctx *ctx);
+
+/* Exact thresholds for K target recurrence rates (Averaged RQA section: the
+ * RR is preselected and eps follows from it).
+ *   series_dev: n float32 samples (device).
+ *   rr: K targets in (0, 1] (host), any order, repeats allowed.
+ *   flags: RQA_SEL_PLAIN or RQA_SEL_LEARNED.
+ *   eps_out[K]: eps_r = the k_r-th smallest key (host).
+ *   k_out[K] (or NULL): k_r.   count_out[K] (or NULL): #{key <= eps_r}.
+ * Outputs follow the order of rr. */
+rqa_status rqa_select_thresholds(rqa_ctx *ctx, const float *series_dev, uint64_t n,
+                                 const rqa_params *p, const double *rr, uint32_t K,
+                                 uint32_t flags, float *eps_out, uint64_t *k_out,
+                                 uint64_t *count_out);
+
+/* Recurrence rate and determinism at K given thresholds in one pass over the
+ * pairs (Eq. 3, Eq. 4), and their mean.
+ *   eps: K thresholds in key units, each >= 0 or +inf, not NaN (host).
+ *   count_out[K]: C_r = #{key <= eps_r};  rr_out[K]: C_r / M;
+ *   det_out[K]: DET_r (NaN when C_r = 0);  det_mean_out[1]: mean of det_out.
+ *   hist_out/hist_len: must be NULL/0 (the full histogram is not built yet).
+ * flags: 0. */
+rqa_status rqa_det_curve(rqa_ctx *ctx, const float *series_dev, uint64_t n,
+                         const rqa_params *p, const float *eps, uint32_t K, uint32_t flags,
+                         uint64_t *count_out, double *rr_out, double *det_out,
+                         double *det_mean_out, uint64_t *hist_out, uint64_t hist_len);
+
+/* The whole path for one series: exact thresholds for the K targets, then RR,
+ * DET and the averaged DET at those thresholds, without a host round trip in
+ * between.  Any output pointer except det_mean_out may be NULL. */
+rqa_status rqa_run(rqa_ctx *ctx, const float *series_dev, uint64_t n, const rqa_params *p,
+                   const double *rr, uint32_t K, uint32_t flags, float *eps_out,
+                   uint64_t *k_out, uint64_t *count_out, double *rr_out, double *det_out,
+                   double *det_mean_out);
+
+/* S independent series in one launch per phase (the paper's ensemble of
+ * independent series, Methodology section).
+ *   concat_dev: all series back to back (device); series s is
+ *     concat_dev[offsets[s] .. offsets[s+1]-1].
+ *   offsets[S+1] (host), p[S] (host), rr[S*K] (host, row s for series s).
+ *   eps_out, rr_out, det_out: S*K (host, row s for series s);
+ *   det_mean_out: S (host).  count_out (or NULL): S*K.
+ * Every series gets exactly the result a single-series rqa_run would give. */
+rqa_status rqa_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
+                     const rqa_params *p, const double *rr, uint32_t K, uint32_t flags,
+                     float *eps_out, double *rr_out, double *det_out, double *det_mean_out,
+                     uint64_t *count_out);
+
+/* Per-phase device times of the last call, in milliseconds, measured with
+ * HIP events on the context stream when timing is enabled (rqa_set_timing).
+ * times_out[0..n_out-1] receives: [0] selection pass 1, [1] pass 2,
+ * [2] pass 3, [3] sweep, [4] everything else (checks, scans, preparation).
+ * Returns the number of entries written. */
+int rqa_phase_times(rqa_ctx *ctx, double *times_out, int n_out);
+
+/* Enable (1) or disable (0) per-phase HIP-event timing on the context. */
+rqa_status rqa_set_timing(rqa_ctx *ctx, int enable);
+
+/* Kernel launch shape: segment length along a diagonal (multiple of 64,
+ * 64..65536) and tiles per work chunk (1..4096).  0 keeps the current value.
+ * Applies to later calls on this context. */
+rqa_status rqa_set_shape(rqa_ctx *ctx, uint32_t segment, uint32_t chunk_tiles);
+
+/* Number of persistent workgroups of every counting launch (selection passes
+ * and sweep).  0 (the default) sizes each launch to one full set of resident
+ * workgroups, at most one per work chunk.  A nonzero value is used as given,
+ * also when it exceeds the number of chunks: the surplus workgroups find the
+ * work queue empty and exit.  Applies to later calls on this context. */
+rqa_status rqa_set_grid(rqa_ctx *ctx, uint32_t workgroups);
+
+/* Human-readable name of a status code (static string). */
+const char *rqa_status_string(rqa_status s);
+
+/* Detail of the last failure on the calling thread (static thread-local
+ * storage, valid until the next call from that thread). */
+const char *rqa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQA_H */

@@ -1,0 +1,692 @@
+// capi.hip -- host runtime and C ABI of the averaged-RQA library (include/rqa.h).
+//
+// A call builds one descriptor per series, uploads it with the targets, and
+// runs the phases on the context stream without a host round trip:
+//   finite check -> [selection: pass 1, scan 1, pass 2, scan 2, pass 3, scan 3]
+//   -> [sweep: rank tables, line sweep] -> one copy of the results to the host.
+// The host then turns the integer counts into RR, DET and the averaged DET in
+// double precision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+using namespace rqa;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+rqa_status fail(rqa_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(RQA_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+enum Phase { PH_P1 = 0, PH_P2 = 1, PH_P3 = 2, PH_SWEEP = 3, PH_OTHER = 4, PH_N = 5 };
+
+}  // namespace
+
+struct rqa_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int num_cu = 256;
+    size_t max_lds = 65536;
+    uint32_t seg = 1024;
+    uint32_t chunk_tiles = 16;
+    uint32_t grid = 0;  // 0: automatic
+    // device pool
+    void* pool = nullptr;
+    size_t pool_bytes = 0;
+    // host staging (pinned)
+    void* host = nullptr;
+    size_t host_bytes = 0;
+    // timing
+    bool timing = false;
+    hipEvent_t ev[2 * PH_N * 8] = {};
+    bool ev_ready = false;
+    double phase_ms[PH_N] = {};
+};
+
+namespace {
+
+struct Series {
+    uint64_t offset;  // element offset into the device buffer
+    uint64_t n;
+    rqa_params p;
+};
+
+rqa_status check_params(const rqa_params* p, uint64_t n, uint64_t* nv_out, uint64_t* M_out)
+{
+    if (!p) return fail(RQA_ERR_INVALID_ARG, "params is NULL");
+    if (p->m == 0 || p->tau == 0) return fail(RQA_ERR_INVALID_ARG, "m and tau must be >= 1");
+    if (p->theiler == 0) return fail(RQA_ERR_INVALID_ARG, "theiler window must be >= 1");
+    if (p->lmin == 0 || p->lmin > (uint32_t)LMIN_MAX)
+        return fail(p->lmin == 0 ? RQA_ERR_INVALID_ARG : RQA_ERR_UNSUPPORTED, "lmin must be in 1..%d", LMIN_MAX);
+    if (p->norm != RQA_NORM_MAX && p->norm != RQA_NORM_EUCLIDEAN)
+        return fail(RQA_ERR_INVALID_ARG, "unknown norm %u", p->norm);
+    if (n >= (1ull << 31)) return fail(RQA_ERR_UNSUPPORTED, "series length must be < 2^31");
+    const uint64_t span = (uint64_t)(p->m - 1) * p->tau;
+    const uint64_t nv = span < n ? n - span : 0;
+    if (nv <= p->theiler) return fail(RQA_ERR_TOO_SHORT, "%llu vectors leave no pair beyond the Theiler window",
+                                      (unsigned long long)nv);
+    const uint64_t a = nv - p->theiler;
+    *nv_out = nv;
+    *M_out = a * (a + 1) / 2;
+    return RQA_OK;
+}
+
+// k = ceil(q * M / 1e9) with q = round(rr * 1e9), clamped to [1, M].
+rqa_status target_rank(double rr, uint64_t M, uint64_t* k)
+{
+    if (!(rr > 0.0) || !(rr <= 1.0)) return fail(RQA_ERR_INVALID_ARG, "RR target %g outside (0, 1]", rr);
+    long long q = llround(rr * 1e9);
+    q = std::min(std::max(q, 1LL), 1000000000LL);
+    const unsigned __int128 prod = (unsigned __int128)(uint64_t)q * M;
+    uint64_t kk = (uint64_t)((prod + 999999999u) / 1000000000u);
+    *k = std::min(std::max<uint64_t>(kk, 1), M);
+    return RQA_OK;
+}
+
+rqa_status check_eps(float e, uint32_t* bits)
+{
+    if (std::isnan(e)) return fail(RQA_ERR_INVALID_ARG, "threshold is NaN");
+    if (e < 0.0f) return fail(RQA_ERR_INVALID_ARG, "threshold %g is negative", (double)e);
+    if (e == 0.0f) e = 0.0f;  // -0 -> +0
+    std::memcpy(bits, &e, 4);
+    return RQA_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+rqa_status ensure_pool(rqa_ctx* c, size_t bytes)
+{
+    if (c->pool_bytes >= bytes) return RQA_OK;
+    const size_t want = std::max(bytes, c->pool_bytes * 3 / 2);
+    if (c->pool) (void)hipFree(c->pool);
+    c->pool = nullptr;
+    c->pool_bytes = 0;
+    if (hipMalloc(&c->pool, want) != hipSuccess) {
+        c->pool = nullptr;
+        (void)hipGetLastError();
+        return fail(RQA_ERR_NOMEM, "hipMalloc of %zu bytes of scratch failed", want);
+    }
+    c->pool_bytes = want;
+    return RQA_OK;
+}
+
+rqa_status ensure_host(rqa_ctx* c, size_t bytes)
+{
+    if (c->host_bytes >= bytes) return RQA_OK;
+    if (c->host) (void)hipHostFree(c->host);
+    c->host = nullptr;
+    c->host_bytes = 0;
+    if (hipHostMalloc(&c->host, bytes, hipHostMallocDefault) != hipSuccess) {
+        c->host = nullptr;
+        (void)hipGetLastError();
+        return fail(RQA_ERR_NOMEM, "hipHostMalloc of %zu bytes failed", bytes);
+    }
+    c->host_bytes = bytes;
+    return RQA_OK;
+}
+
+struct Timer {
+    rqa_ctx* c;
+    int used = 0;
+    int phase[PH_N * 8];
+    Timer(rqa_ctx* ctx) : c(ctx) {}
+    hipError_t begin(int ph)
+    {
+        if (!c->timing || used >= PH_N * 8) return hipSuccess;
+        phase[used] = ph;
+        return hipEventRecord(c->ev[2 * used], c->stream);
+    }
+    hipError_t end()
+    {
+        if (!c->timing || used >= PH_N * 8) return hipSuccess;
+        hipError_t e = hipEventRecord(c->ev[2 * used + 1], c->stream);
+        ++used;
+        return e;
+    }
+    void collect()
+    {
+        for (int i = 0; i < PH_N; ++i) c->phase_ms[i] = 0.0;
+        if (!c->timing) return;
+        for (int i = 0; i < used; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) c->phase_ms[phase[i]] += ms;
+        }
+    }
+};
+
+enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3 };
+
+struct Job {
+    std::vector<Series> series;
+    const float* base = nullptr;     // device
+    uint32_t K = 0;
+    int mode = MODE_BOTH;
+    std::vector<uint64_t> k;         // S*K, selection targets
+    std::vector<uint32_t> eps_bits;  // S*K, sweep-only thresholds
+    // results
+    std::vector<float> eps;
+    std::vector<uint64_t> kout, count_sel, count;
+    std::vector<double> rr, det, det_mean;
+    std::vector<uint64_t> M;
+};
+
+// Runs selection and/or sweep for every series of the job.
+rqa_status run_job(rqa_ctx* c, Job& job)
+{
+    const uint32_t S = (uint32_t)job.series.size();
+    const uint32_t K = job.K;
+    const uint32_t T = c->seg, CT = c->chunk_tiles;
+
+    // descriptors, ordered by kernel variant so each launch sees a contiguous range
+    std::vector<uint32_t> order(S);
+    std::vector<SeriesDesc> sd(S);
+    std::vector<int> sel_var(S), swp_var(S);
+    job.M.assign(S, 0);
+    for (uint32_t s = 0; s < S; ++s) {
+        const Series& z = job.series[s];
+        uint64_t nv, M;
+        rqa_status st = check_params(&z.p, z.n, &nv, &M);
+        if (st) return st;
+        job.M[s] = M;
+        sel_var[s] = select_variant_of(z.p.norm, z.p.m);
+        swp_var[s] = variant_of(z.p.norm, z.p.m, z.p.lmin);
+        order[s] = s;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (swp_var[a] != swp_var[b]) return swp_var[a] < swp_var[b];
+        return job.series[a].p.lmin < job.series[b].p.lmin;
+    });
+    // groups: consecutive device series sharing the sweep variant (and lmin for the generic one)
+    struct Group { uint32_t begin, end; int sel, swp; uint32_t nchunks; };
+    std::vector<Group> groups;
+    uint32_t maxn = 0;
+    for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t s = order[i];
+        const Series& z = job.series[s];
+        const bool same = !groups.empty() && groups.back().swp == swp_var[s] &&
+                          (swp_var[s] % 3 != 0 || job.series[order[groups.back().begin]].p.lmin == z.p.lmin);
+        if (!same) groups.push_back({i, i, sel_var[s], swp_var[s], 0});
+        Group& g = groups.back();
+        g.end = i + 1;
+        const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
+        const uint64_t L0 = nv - z.p.theiler;
+        SeriesDesc& d = sd[i];
+        d.y = job.base + z.offset;
+        d.n = (uint32_t)z.n;
+        d.nv = (uint32_t)nv;
+        d.m = z.p.m;
+        d.tau = z.p.tau;
+        d.norm = z.p.norm;
+        d.w = z.p.theiler;
+        d.lmin = z.p.lmin;
+        d.K = K;
+        d.M = job.M[s];
+        d.T = T;
+        d.q = T / TILE_W;
+        d.B = (uint32_t)((L0 + TILE_W - 1) / TILE_W);
+        d.Smax = (uint32_t)((L0 + T - 1) / T);
+        const uint64_t ntiles = (uint64_t)d.Smax * d.B - (uint64_t)d.q * ((uint64_t)d.Smax * (d.Smax - 1) / 2);
+        if (ntiles >= (1ull << 31)) return fail(RQA_ERR_UNSUPPORTED, "too many tiles; raise the segment length");
+        d.ntiles = (uint32_t)ntiles;
+        d.nchunks = (uint32_t)((ntiles + CT - 1) / CT);
+        d.chunk_begin = g.nchunks;  // chunk numbering restarts in every group
+        d.variant = (uint32_t)swp_var[s];
+        g.nchunks += d.nchunks;
+        maxn = std::max<uint32_t>(maxn, (uint32_t)z.n);
+    }
+
+    // device layout
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_sd = carve(sizeof(SeriesDesc) * S);
+    const size_t o_work = carve(sizeof(SeriesWork) * S);
+    const size_t o_tick = carve(sizeof(uint32_t) * NUM_TICKETS);
+    const size_t o_h1 = carve(sizeof(uint64_t) * S * SEL_N1);
+    const size_t o_h2 = carve(sizeof(uint64_t) * S * K * SEL_N2);
+    const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
+    const size_t zero_end = off;  // tickets and histograms are cleared every call
+    const size_t o_T1 = carve((size_t)S * SEL_N1);
+    const size_t o_T2 = carve((size_t)S * K * SEL_N2);
+    const size_t o_rt = carve(sizeof(uint2) * S * RHO_TABLE);
+    rqa_status st = ensure_pool(c, off);
+    if (st) return st;
+    char* pool = (char*)c->pool;
+    DevBufs all;
+    all.sd = (SeriesDesc*)(pool + o_sd);
+    all.work = (SeriesWork*)(pool + o_work);
+    all.tickets = (uint32_t*)(pool + o_tick);
+    all.h1 = (uint64_t*)(pool + o_h1);
+    all.h2 = (uint64_t*)(pool + o_h2);
+    all.h3 = (uint64_t*)(pool + o_h3);
+    all.T1 = (uint8_t*)(pool + o_T1);
+    all.T2 = (uint8_t*)(pool + o_T2);
+    all.rtab = (uint2*)(pool + o_rt);
+    all.S = S;
+    all.K = K;
+    all.chunk_tiles = CT;
+    all.nchunks = 0;
+
+    // host staging: descriptors + work (in), work (out)
+    const size_t hs_sd = sizeof(SeriesDesc) * S, hs_work = sizeof(SeriesWork) * S;
+    st = ensure_host(c, hs_sd + 2 * hs_work);
+    if (st) return st;
+    SeriesDesc* h_sd = (SeriesDesc*)c->host;
+    SeriesWork* h_work = (SeriesWork*)((char*)c->host + hs_sd);
+    SeriesWork* h_out = (SeriesWork*)((char*)c->host + hs_sd + hs_work);
+    std::memcpy(h_sd, sd.data(), hs_sd);
+    std::memset(h_work, 0, hs_work);
+    for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t s = order[i];
+        for (uint32_t r = 0; r < K; ++r) {
+            if (job.mode & MODE_SELECT) h_work[i].k[r] = job.k[(size_t)s * K + r];
+            else h_work[i].eps_bits[r] = job.eps_bits[(size_t)s * K + r];
+        }
+    }
+
+    Timer tm(c);
+    hipStream_t sm = c->stream;
+    HIP_TRY(tm.begin(PH_OTHER));
+    HIP_TRY(hipMemcpyAsync(all.sd, h_sd, hs_sd, hipMemcpyHostToDevice, sm));
+    HIP_TRY(hipMemcpyAsync(all.work, h_work, hs_work, hipMemcpyHostToDevice, sm));
+    HIP_TRY(launch_zero(sm, pool + o_tick, zero_end - o_tick));
+    HIP_TRY(launch_check_finite(sm, all, maxn));
+    HIP_TRY(tm.end());
+
+    auto view = [&](const Group& g) {
+        DevBufs v = all;
+        v.sd = all.sd + g.begin;
+        v.work = all.work + g.begin;
+        v.h1 = all.h1 + (size_t)g.begin * SEL_N1;
+        v.h2 = all.h2 + (size_t)g.begin * K * SEL_N2;
+        v.h3 = all.h3 + (size_t)g.begin * K * SEL_N3;
+        v.T1 = all.T1 + (size_t)g.begin * SEL_N1;
+        v.T2 = all.T2 + (size_t)g.begin * K * SEL_N2;
+        v.rtab = all.rtab + (size_t)g.begin * RHO_TABLE;
+        v.S = g.end - g.begin;
+        v.nchunks = g.nchunks;
+        return v;
+    };
+
+    uint32_t ticket = 0;
+    auto take = [&](uint32_t n) -> int {
+        if (ticket + n > (uint32_t)NUM_TICKETS) return -1;
+        int t = (int)ticket;
+        ticket += n;
+        return t;
+    };
+
+    if (job.mode & MODE_SELECT) {
+        for (int pass = 1; pass <= 3; ++pass) {
+            HIP_TRY(tm.begin(pass - 1));
+            for (const Group& g : groups) {
+                DevBufs v = view(g);
+                uint32_t block = pass == 1 ? 256 : 1024;
+                uint32_t G = 1, ngroups = 1;
+                if (pass > 1) {
+                    const size_t fixed = select_lds_bytes(pass, K, 0);
+                    const size_t per = pass == 2 ? SEL_N2 * 4 : SEL_N3 * 4;
+                    const size_t room = c->max_lds > fixed ? c->max_lds - fixed : 0;
+                    G = (uint32_t)std::min<size_t>(K, room / per);
+                    if (G == 0) return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass %d", K, pass);
+                    ngroups = (K + G - 1) / G;
+                }
+                const size_t lds = select_lds_bytes(pass, K, G);
+                const int per_cu = select_blocks_per_cu(pass, g.sel, block, lds);
+                const uint32_t grid = c->grid ? c->grid
+                                              : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
+                const int t = take(ngroups);
+                if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
+                HIP_TRY(launch_select_pass(sm, v, pass, g.sel, grid, block, ngroups, G, (uint32_t)t));
+            }
+            HIP_TRY(tm.end());
+            HIP_TRY(tm.begin(PH_OTHER));
+            HIP_TRY(launch_select_scan(sm, all, pass));
+            HIP_TRY(tm.end());
+        }
+    }
+    if (job.mode & MODE_SWEEP) {
+        HIP_TRY(tm.begin(PH_OTHER));
+        HIP_TRY(launch_sweep_prep(sm, all));
+        HIP_TRY(tm.end());
+        HIP_TRY(tm.begin(PH_SWEEP));
+        for (const Group& g : groups) {
+            DevBufs v = view(g);
+            const uint32_t block = 512;
+            const size_t lds = sweep_lds_bytes(K);
+            const int per_cu = sweep_blocks_per_cu(g.swp, block, lds);
+            const uint32_t grid = c->grid ? c->grid
+                                          : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
+            const int t = take(1);
+            if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
+            HIP_TRY(launch_sweep(sm, v, g.swp, grid, block, (uint32_t)t));
+        }
+        HIP_TRY(tm.end());
+    }
+    HIP_TRY(hipMemcpyAsync(h_out, all.work, hs_work, hipMemcpyDeviceToHost, sm));
+    HIP_TRY(hipStreamSynchronize(sm));
+    tm.collect();
+
+    // results, back in caller order
+    job.eps.assign((size_t)S * K, 0.f);
+    job.kout.assign((size_t)S * K, 0);
+    job.count_sel.assign((size_t)S * K, 0);
+    job.count.assign((size_t)S * K, 0);
+    job.rr.assign((size_t)S * K, 0.0);
+    job.det.assign((size_t)S * K, 0.0);
+    job.det_mean.assign(S, 0.0);
+    for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t s = order[i];
+        const SeriesWork& w = h_out[i];
+        if (w.nonfinite) return fail(RQA_ERR_NONFINITE, "series %u holds a NaN or infinite sample", s);
+        if (w.status) return fail(RQA_ERR_DEVICE, "selection of series %u is inconsistent (code %u)", s, w.status);
+        for (uint32_t r = 0; r < K; ++r) {
+            float e;
+            std::memcpy(&e, &w.eps_bits[r], 4);
+            job.eps[(size_t)s * K + r] = e;
+            job.kout[(size_t)s * K + r] = w.k[r];
+            job.count_sel[(size_t)s * K + r] = w.count[r];
+        }
+        if (job.mode & MODE_SWEEP) {
+            const uint32_t Kp = w.Kp;
+            std::vector<uint64_t> C(Kp), D(Kp);
+            uint64_t cr = 0, cl = 0;
+            for (uint32_t j = 0; j < Kp; ++j) {
+                cr += w.hrho[j];
+                cl += w.hlam[j];
+                C[j] = cr;
+                D[j] = cl;
+            }
+            double sum = 0.0;
+            for (uint32_t r = 0; r < K; ++r) {
+                const uint32_t j = w.dmap[r];
+                const uint64_t cnt = C[j];
+                const double det = cnt ? (double)D[j] / (double)cnt : NAN;
+                job.count[(size_t)s * K + r] = cnt;
+                job.rr[(size_t)s * K + r] = (double)cnt / (double)job.M[s];
+                job.det[(size_t)s * K + r] = det;
+                sum += det;
+            }
+            job.det_mean[s] = sum / (double)K;
+        }
+    }
+    return RQA_OK;
+}
+
+rqa_status check_ctx(rqa_ctx* c)
+{
+    if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    return RQA_OK;
+}
+
+rqa_status check_k(uint32_t K)
+{
+    if (K == 0 || K > RQA_MAX_K) return fail(RQA_ERR_INVALID_ARG, "K=%u outside 1..%d", K, RQA_MAX_K);
+    return RQA_OK;
+}
+
+rqa_status check_flags_select(uint32_t flags)
+{
+    if (flags & ~(uint32_t)(RQA_SEL_LEARNED | RQA_FULL_HIST)) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & RQA_FULL_HIST) return fail(RQA_ERR_UNSUPPORTED, "RQA_FULL_HIST is not implemented");
+    if (flags & RQA_SEL_LEARNED) return fail(RQA_ERR_UNSUPPORTED, "no threshold model is loaded");
+    return RQA_OK;
+}
+
+rqa_status single_job(rqa_ctx* c, Job& job, const float* series, uint64_t n, const rqa_params* p,
+                      const double* rr, const float* eps, uint32_t K, int mode)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (!series) return fail(RQA_ERR_INVALID_ARG, "series pointer is NULL");
+    if ((st = check_k(K))) return st;
+    uint64_t nv, M;
+    if ((st = check_params(p, n, &nv, &M))) return st;
+    job.series.push_back({0, n, *p});
+    job.base = series;
+    job.K = K;
+    job.mode = mode;
+    if (mode & MODE_SELECT) {
+        if (!rr) return fail(RQA_ERR_INVALID_ARG, "rr is NULL");
+        job.k.resize(K);
+        for (uint32_t r = 0; r < K; ++r)
+            if ((st = target_rank(rr[r], M, &job.k[r]))) return st;
+    } else {
+        if (!eps) return fail(RQA_ERR_INVALID_ARG, "eps is NULL");
+        job.eps_bits.resize(K);
+        for (uint32_t r = 0; r < K; ++r)
+            if ((st = check_eps(eps[r], &job.eps_bits[r]))) return st;
+    }
+    return run_job(c, job);
+}
+
+}  // namespace
+
+extern "C" {
+
+rqa_status rqa_create(rqa_ctx** out, int device, void* hip_stream)
+{
+    if (!out) return fail(RQA_ERR_INVALID_ARG, "out is NULL");
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(RQA_ERR_INVALID_ARG, "device %d of %d", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(RQA_ERR_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+    rqa_ctx* c = new rqa_ctx();
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    c->max_lds = std::max<size_t>(prop.sharedMemPerBlock, 65536);
+    if (prop.maxSharedMemoryPerMultiProcessor > 0)
+        c->max_lds = std::min<size_t>(std::max<size_t>(c->max_lds, prop.sharedMemPerBlockOptin),
+                                      prop.maxSharedMemoryPerMultiProcessor);
+    if (c->max_lds > 65536 && set_kernel_lds_limits(c->max_lds) != hipSuccess) {
+        (void)hipGetLastError();
+        c->max_lds = 65536;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(RQA_ERR_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return RQA_OK;
+}
+
+void rqa_destroy(rqa_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->pool) (void)hipFree(c->pool);
+    if (c->host) (void)hipHostFree(c->host);
+    if (c->ev_ready)
+        for (auto& e : c->ev) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+rqa_status rqa_set_timing(rqa_ctx* c, int enable)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (enable && !c->ev_ready) {
+        for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+        c->ev_ready = true;
+    }
+    c->timing = enable != 0;
+    return RQA_OK;
+}
+
+int rqa_phase_times(rqa_ctx* c, double* out, int n)
+{
+    if (!c || !out) return 0;
+    int k = std::min(n, (int)PH_N);
+    for (int i = 0; i < k; ++i) out[i] = c->phase_ms[i];
+    return k;
+}
+
+rqa_status rqa_set_shape(rqa_ctx* c, uint32_t segment, uint32_t chunk_tiles)
+{
+    if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
+    if (segment) {
+        if (segment % TILE_W || segment < TILE_W || segment > 65536)
+            return fail(RQA_ERR_INVALID_ARG, "segment %u must be a multiple of 64 in 64..65536", segment);
+        c->seg = segment;
+    }
+    if (chunk_tiles) {
+        if (chunk_tiles > 4096) return fail(RQA_ERR_INVALID_ARG, "chunk_tiles %u > 4096", chunk_tiles);
+        c->chunk_tiles = chunk_tiles;
+    }
+    return RQA_OK;
+}
+
+rqa_status rqa_set_grid(rqa_ctx* c, uint32_t workgroups)
+{
+    if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
+    if (workgroups > 65536) return fail(RQA_ERR_INVALID_ARG, "workgroups %u > 65536", workgroups);
+    c->grid = workgroups;
+    return RQA_OK;
+}
+
+rqa_status rqa_select_thresholds(rqa_ctx* c, const float* series, uint64_t n, const rqa_params* p,
+                                 const double* rr, uint32_t K, uint32_t flags, float* eps_out,
+                                 uint64_t* k_out, uint64_t* count_out)
+{
+    rqa_status st = check_flags_select(flags);
+    if (st) return st;
+    if (!eps_out) return fail(RQA_ERR_INVALID_ARG, "eps_out is NULL");
+    Job job;
+    if ((st = single_job(c, job, series, n, p, rr, nullptr, K, MODE_SELECT))) return st;
+    for (uint32_t r = 0; r < K; ++r) {
+        eps_out[r] = job.eps[r];
+        if (k_out) k_out[r] = job.kout[r];
+        if (count_out) count_out[r] = job.count_sel[r];
+    }
+    return RQA_OK;
+}
+
+rqa_status rqa_det_curve(rqa_ctx* c, const float* series, uint64_t n, const rqa_params* p, const float* eps,
+                         uint32_t K, uint32_t flags, uint64_t* count_out, double* rr_out, double* det_out,
+                         double* det_mean_out, uint64_t* hist_out, uint64_t hist_len)
+{
+    if (flags & RQA_FULL_HIST || hist_out || hist_len)
+        return fail(RQA_ERR_UNSUPPORTED, "the full line-length histogram is not implemented");
+    if (flags) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (!count_out || !rr_out || !det_out || !det_mean_out) return fail(RQA_ERR_INVALID_ARG, "an output is NULL");
+    Job job;
+    rqa_status st = single_job(c, job, series, n, p, nullptr, eps, K, MODE_SWEEP);
+    if (st) return st;
+    for (uint32_t r = 0; r < K; ++r) {
+        count_out[r] = job.count[r];
+        rr_out[r] = job.rr[r];
+        det_out[r] = job.det[r];
+    }
+    *det_mean_out = job.det_mean[0];
+    return RQA_OK;
+}
+
+rqa_status rqa_run(rqa_ctx* c, const float* series, uint64_t n, const rqa_params* p, const double* rr, uint32_t K,
+                   uint32_t flags, float* eps_out, uint64_t* k_out, uint64_t* count_out, double* rr_out,
+                   double* det_out, double* det_mean_out)
+{
+    rqa_status st = check_flags_select(flags);
+    if (st) return st;
+    if (!det_mean_out) return fail(RQA_ERR_INVALID_ARG, "det_mean_out is NULL");
+    Job job;
+    if ((st = single_job(c, job, series, n, p, rr, nullptr, K, MODE_BOTH))) return st;
+    for (uint32_t r = 0; r < K; ++r) {
+        if (eps_out) eps_out[r] = job.eps[r];
+        if (k_out) k_out[r] = job.kout[r];
+        if (count_out) count_out[r] = job.count[r];
+        if (rr_out) rr_out[r] = job.rr[r];
+        if (det_out) det_out[r] = job.det[r];
+    }
+    *det_mean_out = job.det_mean[0];
+    return RQA_OK;
+}
+
+rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets, const rqa_params* p,
+                     const double* rr, uint32_t K, uint32_t flags, float* eps_out, double* rr_out, double* det_out,
+                     double* det_mean_out, uint64_t* count_out)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_flags_select(flags))) return st;
+    if ((st = check_k(K))) return st;
+    if (S == 0 || !concat || !offsets || !p || !rr || !eps_out || !rr_out || !det_out || !det_mean_out)
+        return fail(RQA_ERR_INVALID_ARG, "S is 0 or a required pointer is NULL");
+    Job job;
+    job.base = concat;
+    job.K = K;
+    job.mode = MODE_BOTH;
+    job.k.resize((size_t)S * K);
+    for (uint32_t s = 0; s < S; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(RQA_ERR_INVALID_ARG, "offsets decrease at series %u", s);
+        const uint64_t n = offsets[s + 1] - offsets[s];
+        uint64_t nv, M;
+        if ((st = check_params(&p[s], n, &nv, &M))) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "series %u: %s", s, g_err);
+            return fail(st, "%s", msg);
+        }
+        job.series.push_back({offsets[s], n, p[s]});
+        for (uint32_t r = 0; r < K; ++r)
+            if ((st = target_rank(rr[(size_t)s * K + r], M, &job.k[(size_t)s * K + r]))) return st;
+    }
+    if ((st = run_job(c, job))) return st;
+    for (size_t i = 0; i < (size_t)S * K; ++i) {
+        eps_out[i] = job.eps[i];
+        rr_out[i] = job.rr[i];
+        det_out[i] = job.det[i];
+        if (count_out) count_out[i] = job.count[i];
+    }
+    for (uint32_t s = 0; s < S; ++s) det_mean_out[s] = job.det_mean[s];
+    return RQA_OK;
+}
+
+const char* rqa_status_string(rqa_status s)
+{
+    switch (s) {
+    case RQA_OK: return "ok";
+    case RQA_ERR_INVALID_ARG: return "invalid argument";
+    case RQA_ERR_TOO_SHORT: return "series too short";
+    case RQA_ERR_NONFINITE: return "non-finite sample";
+    case RQA_ERR_DEVICE: return "device error";
+    case RQA_ERR_NOMEM: return "out of device memory";
+    case RQA_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* rqa_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// internal.h -- device data layout shared by the kernels and the host code of
+// the averaged-RQA library.  Not part of the public C ABI (see include/rqa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rqa.h"
+
+namespace rqa {
+
+// One wavefront walks a band of TILE_W consecutive diagonals; lane L owns
+// diagonal d0 + L and steps along it.
+constexpr int TILE_W = 64;
+
+// Radix split of the 31 significant bits of a key (the sign bit is always 0):
+// pass 1 histograms the top SEL_B1 bits for every pair; pass 2 the next SEL_B2
+// bits of keys whose pass-1 prefix holds a target; pass 3 the last SEL_B3 bits.
+constexpr int SEL_B1 = 12;
+constexpr int SEL_B2 = 10;
+constexpr int SEL_B3 = 9;
+constexpr int SEL_SH1 = 31 - SEL_B1;           // 19
+constexpr int SEL_SH2 = SEL_SH1 - SEL_B2;      // 9
+constexpr uint32_t SEL_N1 = 1u << SEL_B1;      // 4096
+constexpr uint32_t SEL_N2 = 1u << SEL_B2;      // 1024
+constexpr uint32_t SEL_N3 = 1u << SEL_B3;      // 512
+constexpr uint8_t NO_SLOT = 0xFF;
+
+// Threshold-rank lookup table of the sweep: RHO_TABLE buckets of the key's
+// bit pattern between the smallest and the largest threshold.
+constexpr int RHO_BITS = 12;
+constexpr uint32_t RHO_TABLE = 1u << RHO_BITS;
+constexpr uint32_t RHO_MULTI = 0x10000u;       // entry.y >= this: >1 threshold in bucket
+
+constexpr int LMIN_MAX = 16;
+
+// Per-series descriptor (device copy built by the host for every call).
+struct SeriesDesc {
+    const float* y;        // device pointer to the series
+    uint32_t n;            // samples
+    uint32_t nv;           // delay vectors n - (m-1) tau
+    uint32_t m, tau, norm, w, lmin;
+    uint32_t K;            // targets / thresholds
+    uint64_t M;            // pairs (nv-w)(nv-w+1)/2
+    uint32_t B;            // bands of TILE_W diagonals: ceil((nv-w)/64)
+    uint32_t T;            // segment length along a diagonal (multiple of 64)
+    uint32_t q;            // T / 64
+    uint32_t Smax;         // segments: ceil((nv-w)/T)
+    uint32_t ntiles;       // (band, segment) tiles
+    uint32_t chunk_begin;  // first global chunk index of this series
+    uint32_t nchunks;      // chunks of this series
+    uint32_t variant;      // kernel variant (norm/m/lmin class), host bookkeeping
+};
+
+// Per-series working state in device memory.
+struct SeriesWork {
+    // exact selection (targets in caller order)
+    uint64_t k[RQA_MAX_K];        // target rank
+    uint64_t below[RQA_MAX_K];    // keys below the target's current bucket
+    uint32_t prefix[RQA_MAX_K];   // resolved high bits of the target's key
+    uint32_t slot[RQA_MAX_K];     // slot of the target in the current pass
+    uint32_t nslots2, nslots3;
+    uint32_t eps_bits[RQA_MAX_K]; // selected (or given) thresholds, caller order
+    uint64_t count[RQA_MAX_K];    // #{key <= eps} from selection
+    // sweep
+    uint32_t esorted[RQA_MAX_K];  // distinct thresholds, ascending
+    uint32_t dmap[RQA_MAX_K];     // caller index -> distinct index
+    uint32_t Kp;                  // distinct thresholds
+    uint32_t shift, emin, emax;   // rank-table geometry
+    uint64_t hrho[RQA_MAX_K + 1]; // cells with rank rho (rho < Kp)
+    uint64_t hlam[RQA_MAX_K + 1]; // cells with line rank lambda (lambda < Kp)
+    uint32_t nonfinite;           // set when a sample is NaN or infinite
+    uint32_t status;              // device-side error bits (0 = fine)
+};
+
+// Device buffers of one call (host-side handle).
+struct DevBufs {
+    SeriesDesc* sd;     // [S]
+    SeriesWork* work;   // [S]
+    uint8_t* T1;        // [S][SEL_N1] pass-1 bucket -> pass-2 slot
+    uint8_t* T2;        // [S][K][SEL_N2] (pass-2 slot, sub-bucket) -> pass-3 slot
+    uint2* rtab;        // [S][RHO_TABLE] sweep rank table
+    uint64_t* h1;       // [S][SEL_N1]
+    uint64_t* h2;       // [S][K][SEL_N2]
+    uint64_t* h3;       // [S][K][SEL_N3]
+    uint32_t* tickets;  // work-queue counters, one per launch
+    uint32_t S, K;
+    uint32_t nchunks;   // over all series
+    uint32_t chunk_tiles;
+};
+
+constexpr int NUM_TICKETS = 256;
+
+// Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_zero(hipStream_t st, void* p, size_t bytes);
+hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn);
+hipError_t launch_select_pass(hipStream_t st, const DevBufs& b, int pass, int variant,
+                              uint32_t grid, uint32_t block, uint32_t groups, uint32_t group_slots,
+                              uint32_t ticket_base);
+hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass);
+hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b);
+hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, uint32_t grid,
+                        uint32_t block, uint32_t ticket);
+
+// Kernel variants: norm x embedding class x line-length class.
+enum MClass { MC_ANY = 0, MC_1 = 1, MC_3 = 3 };
+int variant_of(uint32_t norm, uint32_t m, uint32_t lmin);
+int select_variant_of(uint32_t norm, uint32_t m);
+
+// Dynamic LDS bytes of each kernel for a K and group size.
+size_t select_lds_bytes(int pass, uint32_t K, uint32_t group_slots);
+size_t sweep_lds_bytes(uint32_t K);
+
+// Occupancy helpers (kernels.hip): max resident workgroups per CU.
+int select_blocks_per_cu(int pass, int variant, uint32_t block, size_t lds);
+int sweep_blocks_per_cu(int variant, uint32_t block, size_t lds);
+hipError_t set_kernel_lds_limits(size_t max_dyn_lds);
+
+}  // namespace rqa

@@ -1,0 +1,883 @@
+// kernels.hip -- gfx950 kernels of the averaged-RQA hot path.
+//
+// Work decomposition (every kernel): the pairs (i, j = i + d) of one series
+// form the upper triangle of diagonals d = w .. nv-1.  A tile is one band of
+// 64 consecutive diagonals times one segment of T steps along them; lane L of
+// the wavefront that owns the tile walks diagonal d0 + L.  Tiles are
+// enumerated segment-major (all bands of segment 0, then of segment 1, ...),
+// grouped into chunks of consecutive tiles of one series, and chunks are
+// handed to persistent workgroups through an atomic ticket.  The recurrence
+// matrix is never stored: every key is recomputed from the series.
+//
+// Keys follow Eq. 1 of the paper with the maximum norm, or the squared
+// Euclidean norm folded left over the embedding components; all float
+// arithmetic is binary32 with round-to-nearest-even and no contraction, so the
+// keys (and every count derived from them) are bit-identical to a plain CPU
+// evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace rqa {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ void tile_coords(const SeriesDesc& sd, uint32_t tile, uint32_t& band,
+                                            uint32_t& seg)
+{
+    // Segment s holds B - s*q bands, so tiles before segment s number
+    // P(s) = s*B - q*s*(s-1)/2.  Invert with the quadratic formula and fix up.
+    const uint64_t B = sd.B, q = sd.q;
+    auto P = [&](uint64_t s) -> uint64_t { return s * B - q * ((s * (s - 1)) / 2); };
+    const double Bq = (double)B + 0.5 * (double)q;
+    const double disc = Bq * Bq - 2.0 * (double)q * (double)tile;
+    const double est = (Bq - sqrt(disc > 0.0 ? disc : 0.0)) / (double)q;
+    uint64_t s = est > 0.0 ? (uint64_t)est : 0;
+    if (s > sd.Smax - 1) s = sd.Smax - 1;
+    while (s > 0 && P(s) > tile) --s;
+    while (s + 1 < sd.Smax && P(s + 1) <= tile) ++s;
+    seg = (uint32_t)s;
+    band = (uint32_t)(tile - P(s));
+}
+
+__device__ __forceinline__ uint32_t find_series(const SeriesDesc* __restrict__ sds, uint32_t S,
+                                                uint32_t chunk)
+{
+    uint32_t lo = 0, hi = S;  // largest s with chunk_begin <= chunk
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (sds[mid].chunk_begin <= chunk) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Distance key of vectors i and j: component k is y[i + (m-1-k) tau].
+template <int NORM, int MC>
+__device__ __forceinline__ float pair_key(const float* __restrict__ y, int i, int j, int m, int tau)
+{
+    float acc = 0.0f;
+    if constexpr (MC > 0) {
+#pragma unroll
+        for (int k = 0; k < MC; ++k) {
+            const int off = (MC - 1 - k) * tau;
+            const float d = y[i + off] - y[j + off];
+            if constexpr (NORM == RQA_NORM_MAX) acc = fmaxf(acc, fabsf(d));
+            else acc = (k == 0) ? d * d : acc + d * d;
+        }
+    } else {
+        int off = (m - 1) * tau;
+        for (int k = 0; k < m; ++k, off -= tau) {
+            const float d = y[i + off] - y[j + off];
+            if constexpr (NORM == RQA_NORM_MAX) acc = fmaxf(acc, fabsf(d));
+            else acc = (k == 0) ? d * d : acc + d * d;
+        }
+    }
+    return acc;
+}
+
+// Geometry of one tile for the calling lane.
+struct TileGeo {
+    int d;     // this lane's diagonal
+    int d0;    // the band's first diagonal (always < nv)
+    int len;   // cells on this lane's diagonal (0 past the last diagonal)
+    int t0;    // first step of the segment
+    int t1;    // one past the last step of the segment on the band's longest diagonal
+};
+
+__device__ __forceinline__ TileGeo tile_geo(const SeriesDesc& sd, uint32_t tile, int lane)
+{
+    uint32_t band, seg;
+    tile_coords(sd, tile, band, seg);
+    TileGeo g;
+    g.d0 = (int)(sd.w + band * TILE_W);
+    g.d = g.d0 + lane;
+    g.len = g.d < (int)sd.nv ? (int)sd.nv - g.d : 0;
+    g.t0 = (int)(seg * sd.T);
+    const int len0 = (int)sd.nv - g.d0;
+    g.t1 = min(g.t0 + (int)sd.T, len0);
+    return g;
+}
+
+// ------------------------------------------------------------------ zero / checks
+
+__global__ void k_zero(uint32_t* p, size_t words)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_zero(hipStream_t st, void* p, size_t bytes)
+{
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    uint32_t grid = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, st, (uint32_t*)p, words);
+    return hipGetLastError();
+}
+
+__global__ void k_check_finite(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works)
+{
+    const SeriesDesc& sd = sds[blockIdx.y];
+    bool bad = false;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sd.n; i += gridDim.x * blockDim.x) {
+        const uint32_t u = __float_as_uint(sd.y[i]);
+        bad |= (u & 0x7F800000u) == 0x7F800000u;
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&works[blockIdx.y].nonfinite, 1u);
+}
+
+hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn)
+{
+    uint32_t gx = std::min<uint32_t>((maxn + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_check_finite, dim3(gx, b.S), dim3(256), 0, st, b.sd, b.work);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ selection
+
+// Persistent work loop shared by the counting kernels: grab chunks from the
+// ticket, switch per-series LDS state when the series changes, process the
+// chunk's tiles one per wavefront, flush accumulated counts when the series
+// changes, when 32-bit LDS counters could overflow, and at the end.
+template <class Body>
+__device__ __forceinline__ void chunk_loop(const SeriesDesc* __restrict__ sds, uint32_t S,
+                                           uint32_t nchunks, uint32_t chunk_tiles,
+                                           uint32_t* __restrict__ ticket, Body& body)
+{
+    __shared__ uint32_t s_chunk;
+    uint32_t cur = 0xFFFFFFFFu;
+    uint64_t acc = 0;
+    const int wave = threadIdx.x / TILE_W;
+    const int nwaves = blockDim.x / TILE_W;
+    const int lane = threadIdx.x % TILE_W;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_chunk = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t c = s_chunk;
+        if (c >= nchunks) {
+            // queue drained (possibly before this workgroup drew its first chunk)
+            if (cur != 0xFFFFFFFFu) body.flush(cur);
+            break;
+        }
+        const uint32_t s = find_series(sds, S, c);
+        const SeriesDesc& sd = sds[s];
+        const uint64_t chunk_cells = (uint64_t)chunk_tiles * TILE_W * sd.T;
+        if (s != cur || acc + chunk_cells > 0xFFFFFFFFull) {
+            if (cur != 0xFFFFFFFFu) body.flush(cur);
+            __syncthreads();
+            body.begin(s);
+            __syncthreads();
+            cur = s;
+            acc = 0;
+        }
+        if (body.active) {
+            const uint32_t lc = c - sd.chunk_begin;
+            const uint32_t tb = lc * chunk_tiles;
+            const uint32_t te = min(tb + chunk_tiles, sd.ntiles);
+            for (uint32_t tile = tb + wave; tile < te; tile += nwaves) body.tile(sd, tile, lane);
+        }
+        acc += chunk_cells;
+    }
+}
+
+// Pass 1: histogram of the top SEL_B1 bits of every key.
+template <int NORM, int MC>
+struct SelPass1 {
+    uint32_t* bins;   // LDS [SEL_N1]
+    uint64_t* h1;     // global [S][SEL_N1]
+    bool active = true;
+    __device__ void begin(uint32_t)
+    {
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) bins[i] = 0u;
+    }
+    __device__ void flush(uint32_t s)
+    {
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) {
+            const uint32_t v = bins[i];
+            if (v) atomicAdd((unsigned long long*)&h1[(size_t)s * SEL_N1 + i], (unsigned long long)v);
+        }
+    }
+    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    {
+        const TileGeo g = tile_geo(sd, tile_id, lane);
+        const float* __restrict__ y = sd.y;
+        const int m = sd.m, tau = sd.tau;
+        for (int x = g.t0; x < g.t1; ++x) {
+            if (x < g.len) {
+                const uint32_t u = __float_as_uint(pair_key<NORM, MC>(y, x, x + g.d, m, tau)) & 0x7FFFFFFFu;
+                atomicAdd(&bins[u >> SEL_SH1], 1u);
+            }
+        }
+    }
+};
+
+// Pass 2: for keys whose pass-1 bucket holds a target (slot in [lo, lo+G)),
+// histogram the next SEL_B2 bits per slot.
+template <int NORM, int MC>
+struct SelPass2 {
+    uint8_t* sT1;     // LDS [SEL_N1]
+    uint32_t* bins;   // LDS [G][SEL_N2]
+    const uint8_t* T1;
+    const SeriesWork* works;
+    uint64_t* h2;     // global [S][K][SEL_N2]
+    uint32_t K, G, lo, hi;
+    bool active = true;
+    __device__ void begin(uint32_t s)
+    {
+        const uint32_t ns = works[s].nslots2;
+        hi = min(lo + G, ns);
+        active = lo < ns;
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
+        for (uint32_t i = threadIdx.x; i < G * SEL_N2; i += blockDim.x) bins[i] = 0u;
+    }
+    __device__ void flush(uint32_t s)
+    {
+        if (!active) return;
+        const uint32_t n = (hi - lo) * SEL_N2;
+        uint64_t* dst = h2 + ((size_t)s * K + lo) * SEL_N2;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t v = bins[i];
+            if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
+        }
+    }
+    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    {
+        const TileGeo g = tile_geo(sd, tile_id, lane);
+        const float* __restrict__ y = sd.y;
+        const int m = sd.m, tau = sd.tau;
+        for (int x = g.t0; x < g.t1; ++x) {
+            if (x < g.len) {
+                const uint32_t u = __float_as_uint(pair_key<NORM, MC>(y, x, x + g.d, m, tau)) & 0x7FFFFFFFu;
+                const uint32_t sl = sT1[u >> SEL_SH1];
+                if (sl >= lo && sl < hi)
+                    atomicAdd(&bins[(sl - lo) * SEL_N2 + ((u >> SEL_SH2) & (SEL_N2 - 1))], 1u);
+            }
+        }
+    }
+};
+
+// Pass 3: for keys whose 22-bit prefix holds a target (pass-3 slot in
+// [lo, lo+G)), histogram the last SEL_B3 bits per slot.
+template <int NORM, int MC>
+struct SelPass3 {
+    uint8_t* sT1;     // LDS [SEL_N1]
+    uint8_t* sT2;     // LDS [K][SEL_N2]
+    uint32_t* bins;   // LDS [G][SEL_N3]
+    const uint8_t* T1;
+    const uint8_t* T2;
+    const SeriesWork* works;
+    uint64_t* h3;     // global [S][K][SEL_N3]
+    uint32_t K, G, lo, hi;
+    bool active = true;
+    __device__ void begin(uint32_t s)
+    {
+        const uint32_t ns = works[s].nslots3;
+        const uint32_t n2 = works[s].nslots2;
+        hi = min(lo + G, ns);
+        active = lo < ns;
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
+        for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x)
+            sT2[i] = T2[(size_t)s * K * SEL_N2 + i];
+        for (uint32_t i = threadIdx.x; i < G * SEL_N3; i += blockDim.x) bins[i] = 0u;
+    }
+    __device__ void flush(uint32_t s)
+    {
+        if (!active) return;
+        const uint32_t n = (hi - lo) * SEL_N3;
+        uint64_t* dst = h3 + ((size_t)s * K + lo) * SEL_N3;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t v = bins[i];
+            if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
+        }
+    }
+    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    {
+        const TileGeo g = tile_geo(sd, tile_id, lane);
+        const float* __restrict__ y = sd.y;
+        const int m = sd.m, tau = sd.tau;
+        for (int x = g.t0; x < g.t1; ++x) {
+            if (x < g.len) {
+                const uint32_t u = __float_as_uint(pair_key<NORM, MC>(y, x, x + g.d, m, tau)) & 0x7FFFFFFFu;
+                const uint32_t s2 = sT1[u >> SEL_SH1];
+                if (s2 != NO_SLOT) {
+                    const uint32_t s3 = sT2[s2 * SEL_N2 + ((u >> SEL_SH2) & (SEL_N2 - 1))];
+                    if (s3 >= lo && s3 < hi) atomicAdd(&bins[(s3 - lo) * SEL_N3 + (u & (SEL_N3 - 1))], 1u);
+                }
+            }
+        }
+    }
+};
+
+template <int PASS, int NORM, int MC>
+__global__ void __launch_bounds__(1024)
+k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
+         uint32_t* __restrict__ tickets, SeriesWork* __restrict__ works, const uint8_t* __restrict__ T1,
+         const uint8_t* __restrict__ T2, uint64_t* __restrict__ hist, uint32_t K, uint32_t G)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* ticket = tickets + blockIdx.y;
+    if constexpr (PASS == 1) {
+        SelPass1<NORM, MC> body{(uint32_t*)smem, hist};
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+    } else if constexpr (PASS == 2) {
+        SelPass2<NORM, MC> body;
+        body.sT1 = (uint8_t*)smem;
+        body.bins = (uint32_t*)(smem + SEL_N1);
+        body.T1 = T1;
+        body.works = works;
+        body.h2 = hist;
+        body.K = K;
+        body.G = G;
+        body.lo = blockIdx.y * G;
+        body.hi = body.lo;
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+    } else {
+        SelPass3<NORM, MC> body;
+        body.sT1 = (uint8_t*)smem;
+        body.sT2 = (uint8_t*)(smem + SEL_N1);
+        body.bins = (uint32_t*)(smem + SEL_N1 + (size_t)K * SEL_N2);
+        body.T1 = T1;
+        body.T2 = T2;
+        body.works = works;
+        body.h3 = hist;
+        body.K = K;
+        body.G = G;
+        body.lo = blockIdx.y * G;
+        body.hi = body.lo;
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+    }
+}
+
+size_t select_lds_bytes(int pass, uint32_t K, uint32_t G)
+{
+    if (pass == 1) return SEL_N1 * 4;
+    if (pass == 2) return SEL_N1 + (size_t)G * SEL_N2 * 4;
+    return SEL_N1 + (size_t)K * SEL_N2 + (size_t)G * SEL_N3 * 4;
+}
+
+int select_variant_of(uint32_t norm, uint32_t m)
+{
+    const int mc = (m == 1) ? 1 : (m == 3) ? 2 : 0;
+    return (int)norm * 3 + mc;
+}
+
+using SelFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*,
+                       const uint8_t*, const uint8_t*, uint64_t*, uint32_t, uint32_t);
+
+template <int PASS>
+static SelFn select_fn(int variant)
+{
+    switch (variant) {
+    case 0: return k_select<PASS, RQA_NORM_MAX, MC_ANY>;
+    case 1: return k_select<PASS, RQA_NORM_MAX, MC_1>;
+    case 2: return k_select<PASS, RQA_NORM_MAX, MC_3>;
+    case 3: return k_select<PASS, RQA_NORM_EUCLIDEAN, MC_ANY>;
+    case 4: return k_select<PASS, RQA_NORM_EUCLIDEAN, MC_1>;
+    default: return k_select<PASS, RQA_NORM_EUCLIDEAN, MC_3>;
+    }
+}
+
+static SelFn select_fn_pass(int pass, int variant)
+{
+    if (pass == 1) return select_fn<1>(variant);
+    if (pass == 2) return select_fn<2>(variant);
+    return select_fn<3>(variant);
+}
+
+hipError_t launch_select_pass(hipStream_t st, const DevBufs& b, int pass, int variant, uint32_t grid,
+                              uint32_t block, uint32_t groups, uint32_t G, uint32_t ticket_base)
+{
+    const size_t lds = select_lds_bytes(pass, b.K, G);
+    uint64_t* hist = pass == 1 ? b.h1 : pass == 2 ? b.h2 : b.h3;
+    hipLaunchKernelGGL(select_fn_pass(pass, variant), dim3(grid, groups), dim3(block), lds, st, b.sd, b.S,
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket_base, b.work, b.T1, b.T2, hist, b.K, G);
+    return hipGetLastError();
+}
+
+int select_blocks_per_cu(int pass, int variant, uint32_t block, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_fn_pass(pass, variant), (int)block, lds) !=
+        hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+// ------------------------------------------------------------------ scans
+
+// Inclusive prefix sums of n (multiple of blockDim.x) u64 values into LDS.
+__device__ void block_cumsum(const uint64_t* __restrict__ src, uint64_t* cum, uint32_t n)
+{
+    __shared__ uint64_t part[1024];
+    const uint32_t per = n / blockDim.x;
+    const uint32_t base = threadIdx.x * per;
+    uint64_t s = 0;
+    for (uint32_t i = 0; i < per; ++i) {
+        s += src[base + i];
+        cum[base + i] = s;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (uint32_t t = 0; t < blockDim.x; ++t) {
+            const uint64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const uint64_t off = part[threadIdx.x];
+    for (uint32_t i = 0; i < per; ++i) cum[base + i] += off;
+    __syncthreads();
+}
+
+// First index i in [0, n) with cum[i] >= k (cum inclusive, nondecreasing);
+// n-1 if none.
+__device__ __forceinline__ uint32_t first_reaching(const uint64_t* cum, uint32_t n, uint64_t k)
+{
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cum[mid] >= k) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Sort v[0..n) ascending and drop repeats; returns the distinct count.
+__device__ uint32_t sort_unique(uint32_t* v, uint32_t n)
+{
+    for (uint32_t i = 1; i < n; ++i) {
+        const uint32_t x = v[i];
+        uint32_t j = i;
+        while (j > 0 && v[j - 1] > x) { v[j] = v[j - 1]; --j; }
+        v[j] = x;
+    }
+    uint32_t u = 0;
+    for (uint32_t i = 0; i < n; ++i)
+        if (u == 0 || v[i] != v[u - 1]) v[u++] = v[i];
+    return u;
+}
+
+__device__ __forceinline__ uint32_t index_of(const uint32_t* v, uint32_t n, uint32_t x)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (v[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// After pass 1: locate each target's bucket, assign pass-2 slots, fill T1.
+__global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                               uint8_t* __restrict__ T1, const uint64_t* __restrict__ h1)
+{
+    __shared__ uint64_t cum[SEL_N1];
+    __shared__ uint32_t uniq[RQA_MAX_K];
+    __shared__ uint32_t nuniq;
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    block_cumsum(h1 + (size_t)s * SEL_N1, cum, SEL_N1);
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        const uint64_t k = w.k[r];
+        const uint32_t b = first_reaching(cum, SEL_N1, k);
+        if (cum[b] < k) atomicOr(&w.status, 1u);
+        w.prefix[r] = b;
+        w.below[r] = b ? cum[b - 1] : 0;
+        uniq[r] = b;
+    }
+    uint8_t* t1 = T1 + (size_t)s * SEL_N1;
+    for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) t1[i] = NO_SLOT;
+    __syncthreads();
+    if (threadIdx.x == 0) nuniq = sort_unique(uniq, K);
+    __syncthreads();
+    const uint32_t nu = nuniq;
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
+    for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) t1[uniq[u]] = (uint8_t)u;
+    if (threadIdx.x == 0) w.nslots2 = nu;
+}
+
+// After pass 2: resolve SEL_B2 more bits per target, assign pass-3 slots,
+// fill T2 (per pass-2 slot and sub-bucket).
+__global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2)
+{
+    __shared__ uint32_t uniq[RQA_MAX_K];
+    __shared__ uint32_t nuniq;
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    uint8_t* t2 = T2 + (size_t)s * K * SEL_N2;
+    const uint32_t n2 = w.nslots2;
+    for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) t2[i] = NO_SLOT;
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        const uint64_t* h = h2 + ((size_t)s * K + w.slot[r]) * SEL_N2;
+        const uint64_t want = w.k[r] - w.below[r];
+        uint64_t run = 0;
+        uint32_t c = 0;
+        for (; c < SEL_N2; ++c) {
+            if (run + h[c] >= want) break;
+            run += h[c];
+        }
+        if (c == SEL_N2) { c = SEL_N2 - 1; atomicOr(&w.status, 2u); }
+        w.below[r] += run;
+        w.prefix[r] = (w.prefix[r] << SEL_B2) | c;
+        uniq[r] = w.prefix[r];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) nuniq = sort_unique(uniq, K);
+    __syncthreads();
+    const uint32_t nu = nuniq;
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        const uint32_t u = index_of(uniq, nu, w.prefix[r]);
+        const uint32_t s2 = w.slot[r];
+        t2[s2 * SEL_N2 + (w.prefix[r] & (SEL_N2 - 1))] = (uint8_t)u;
+    }
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
+    if (threadIdx.x == 0) w.nslots3 = nu;
+}
+
+// After pass 3: the last SEL_B3 bits give the threshold; count = #{key <= eps}.
+__global__ void __launch_bounds__(256) k_scan3(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                               const uint64_t* __restrict__ h3)
+{
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        const uint64_t* h = h3 + ((size_t)s * K + w.slot[r]) * SEL_N3;
+        const uint64_t want = w.k[r] - w.below[r];
+        uint64_t run = 0;
+        uint32_t c = 0;
+        for (; c < SEL_N3; ++c) {
+            if (run + h[c] >= want) break;
+            run += h[c];
+        }
+        if (c == SEL_N3) { c = SEL_N3 - 1; atomicOr(&w.status, 4u); }
+        w.eps_bits[r] = (w.prefix[r] << SEL_B3) | c;
+        w.count[r] = w.below[r] + run + h[c];
+    }
+}
+
+hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass)
+{
+    if (pass == 1) hipLaunchKernelGGL(k_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T1, b.h1);
+    else if (pass == 2) hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2);
+    else hipLaunchKernelGGL(k_scan3, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.h3);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sweep
+
+// Rank of a key among the distinct sorted thresholds e_0 < ... < e_{Kp-1}:
+// rho = #{e < key}.  The pair recurs at threshold j iff rho <= j.  The bucket
+// of the key (clamped to [e_0, e_{Kp-1}]) gives #{e below the bucket} and the
+// bucket's first threshold; buckets holding several thresholds fall back to
+// comparing against each of them.
+struct RhoCtx {
+    const uint2* table;     // LDS [RHO_TABLE]: x = first threshold in bucket (or ~0), y = rank base
+    const uint32_t* es;     // LDS [Kp] distinct thresholds
+    uint32_t emin, emax, shift, Kp;
+};
+
+__device__ __forceinline__ uint32_t rho_of(uint32_t u, const RhoCtx& c)
+{
+    const uint32_t cl = min(max(u, c.emin), c.emax);
+    const uint2 e = c.table[(cl >> c.shift) & (RHO_TABLE - 1)];
+    uint32_t r = e.y + (u > e.x ? 1u : 0u);
+    if (e.y >= RHO_MULTI) {
+        const uint32_t base = e.y & 0xFFFFu, cnt = e.y >> 16;
+        r = base;
+        for (uint32_t i = 0; i < cnt; ++i) r += (u > c.es[base + i]) ? 1u : 0u;
+    }
+    return r;
+}
+
+template <int NORM, int MC>
+__device__ __forceinline__ uint32_t rho_at(const SeriesDesc& sd, const TileGeo& g, int x, const RhoCtx& rc)
+{
+    const bool ok = (x >= 0) && (x < g.len);
+    const int i = ok ? x : 0;
+    const int j = ok ? x + g.d : g.d0;
+    const uint32_t u = __float_as_uint(pair_key<NORM, MC>(sd.y, i, j, sd.m, sd.tau)) & 0x7FFFFFFFu;
+    const uint32_t r = rho_of(u, rc);
+    return ok ? r : rc.Kp;
+}
+
+// Line rank lambda_t: the smallest distinct-threshold index at which cell t
+// lies on a diagonal line of length >= lmin, i.e. the minimum over windows of
+// lmin consecutive cells containing t of the window's largest rho (cells
+// outside the diagonal have rho = Kp).  lmin = 2: max(rho_t, min(rho_{t-1},
+// rho_{t+1})).
+template <int NORM, int MC, int LMC>
+struct SweepBody {
+    uint2* stab;          // LDS [RHO_TABLE]
+    uint32_t* ses;        // LDS [RQA_MAX_K]
+    uint32_t* brho;       // LDS [Kcap][64]
+    uint32_t* blam;       // LDS [Kcap][64]
+    const uint2* rtab;    // global [S][RHO_TABLE]
+    SeriesWork* works;
+    uint32_t Kcap;
+    RhoCtx rc;
+    uint32_t lmin;
+    bool active = true;
+
+    __device__ void begin(uint32_t s)
+    {
+        const SeriesWork& w = works[s];
+        for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RHO_TABLE + i];
+        for (uint32_t i = threadIdx.x; i < RQA_MAX_K; i += blockDim.x) ses[i] = w.esorted[i];
+        for (uint32_t i = threadIdx.x; i < Kcap * TILE_W; i += blockDim.x) { brho[i] = 0u; blam[i] = 0u; }
+        rc.table = stab;
+        rc.es = ses;
+        rc.emin = w.emin;
+        rc.emax = w.emax;
+        rc.shift = w.shift;
+        rc.Kp = w.Kp;
+    }
+    __device__ void flush(uint32_t s)
+    {
+        SeriesWork& w = works[s];
+        const uint32_t Kp = rc.Kp;
+        for (uint32_t j = threadIdx.x; j < 2 * Kp; j += blockDim.x) {
+            const uint32_t* row = (j < Kp) ? brho + j * TILE_W : blam + (j - Kp) * TILE_W;
+            uint64_t sum = 0;
+            for (int l = 0; l < TILE_W; ++l) sum += row[l];
+            if (sum) atomicAdd((unsigned long long*)((j < Kp) ? &w.hrho[j] : &w.hlam[j - Kp]),
+                               (unsigned long long)sum);
+        }
+    }
+    __device__ __forceinline__ void emit(uint32_t rho, uint32_t lam, int lane)
+    {
+        if (rho < rc.Kp) atomicAdd(&brho[rho * TILE_W + lane], 1u);
+        if (lam < rc.Kp) atomicAdd(&blam[lam * TILE_W + lane], 1u);
+    }
+    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    {
+        const TileGeo g = tile_geo(sd, tile_id, lane);
+        if constexpr (LMC == 1) {
+            for (int x = g.t0; x < g.t1; ++x) {
+                const uint32_t r = rho_at<NORM, MC>(sd, g, x, rc);
+                emit(r, r, lane);
+            }
+        } else if constexpr (LMC == 2) {
+            uint32_t rm1 = rho_at<NORM, MC>(sd, g, g.t0 - 1, rc);
+            uint32_t r0 = rho_at<NORM, MC>(sd, g, g.t0, rc);
+            for (int x = g.t0; x < g.t1; ++x) {
+                const uint32_t rp1 = rho_at<NORM, MC>(sd, g, x + 1, rc);
+                emit(r0, max(r0, min(rm1, rp1)), lane);
+                rm1 = r0;
+                r0 = rp1;
+            }
+        } else {
+            // general lmin <= LMIN_MAX: rings of the last lmin ranks and of the
+            // last lmin window maxima; output lags the newest rank by h = lmin-1.
+            const int h = (int)lmin - 1;
+            uint32_t rr[LMIN_MAX], ww[LMIN_MAX];
+#pragma unroll
+            for (int i = 0; i < LMIN_MAX; ++i) { rr[i] = rc.Kp; ww[i] = rc.Kp; }
+            for (int x = g.t0 - h; x < g.t1 + h; ++x) {
+                const uint32_t r = rho_at<NORM, MC>(sd, g, x, rc);
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX - 1; ++i) rr[i] = rr[i + 1];
+                rr[LMIN_MAX - 1] = r;
+                uint32_t wmax = 0, rold = rc.Kp;
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX; ++i) {
+                    if (i >= LMIN_MAX - 1 - h) wmax = max(wmax, rr[i]);
+                    if (i == LMIN_MAX - 1 - h) rold = rr[i];
+                }
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX - 1; ++i) ww[i] = ww[i + 1];
+                ww[LMIN_MAX - 1] = wmax;
+                if (x >= g.t0 + h) {
+                    uint32_t lam = rc.Kp;
+#pragma unroll
+                    for (int i = 0; i < LMIN_MAX; ++i)
+                        if (i >= LMIN_MAX - 1 - h) lam = min(lam, ww[i]);
+                    emit(rold, lam, lane);
+                }
+            }
+        }
+    }
+};
+
+template <int NORM, int MC, int LMC>
+__global__ void __launch_bounds__(512)
+k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
+        uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
+        uint32_t Kcap)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    SweepBody<NORM, MC, LMC> body;
+    body.stab = (uint2*)smem;
+    body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
+    body.brho = body.ses + RQA_MAX_K;
+    body.blam = body.brho + (size_t)Kcap * TILE_W;
+    body.rtab = rtab;
+    body.works = works;
+    body.Kcap = Kcap;
+    body.lmin = 0;
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+}
+
+// The generic-lmin body needs the series' lmin; it is uniform per launch
+// because launches group series by variant, so read it from the first series.
+template <int NORM, int MC>
+__global__ void __launch_bounds__(512)
+k_sweep_lgen(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
+             uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
+             uint32_t Kcap)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    SweepBody<NORM, MC, 0> body;
+    body.stab = (uint2*)smem;
+    body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
+    body.brho = body.ses + RQA_MAX_K;
+    body.blam = body.brho + (size_t)Kcap * TILE_W;
+    body.rtab = rtab;
+    body.works = works;
+    body.Kcap = Kcap;
+    body.lmin = sds[0].lmin;
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+}
+
+size_t sweep_lds_bytes(uint32_t Kcap)
+{
+    return RHO_TABLE * sizeof(uint2) + RQA_MAX_K * 4 + 2 * (size_t)Kcap * TILE_W * 4;
+}
+
+int variant_of(uint32_t norm, uint32_t m, uint32_t lmin)
+{
+    const int lc = (lmin == 1) ? 1 : (lmin == 2) ? 2 : 0;
+    return select_variant_of(norm, m) * 3 + lc;
+}
+
+using SweepFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*,
+                         const uint2*, uint32_t);
+
+template <int NORM, int MC>
+static SweepFn sweep_fn_l(int lc)
+{
+    if (lc == 1) return k_sweep<NORM, MC, 1>;
+    if (lc == 2) return k_sweep<NORM, MC, 2>;
+    return k_sweep_lgen<NORM, MC>;
+}
+
+static SweepFn sweep_fn(int variant)
+{
+    const int lc = variant % 3;
+    switch (variant / 3) {
+    case 0: return sweep_fn_l<RQA_NORM_MAX, MC_ANY>(lc);
+    case 1: return sweep_fn_l<RQA_NORM_MAX, MC_1>(lc);
+    case 2: return sweep_fn_l<RQA_NORM_MAX, MC_3>(lc);
+    case 3: return sweep_fn_l<RQA_NORM_EUCLIDEAN, MC_ANY>(lc);
+    case 4: return sweep_fn_l<RQA_NORM_EUCLIDEAN, MC_1>(lc);
+    default: return sweep_fn_l<RQA_NORM_EUCLIDEAN, MC_3>(lc);
+    }
+}
+
+hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, uint32_t grid, uint32_t block,
+                        uint32_t ticket)
+{
+    hipLaunchKernelGGL(sweep_fn(variant), dim3(grid), dim3(block), sweep_lds_bytes(b.K), st, b.sd, b.S,
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, b.K);
+    return hipGetLastError();
+}
+
+int sweep_blocks_per_cu(int variant, uint32_t block, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(variant), (int)block, lds) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+// Per series: distinct sorted thresholds, the caller->distinct map and the
+// rank table.  The table spans the buckets (key >> shift) from the smallest
+// to the largest threshold, with the smallest shift that fits RHO_TABLE
+// buckets; bucket a (mod RHO_TABLE) stores the number of thresholds below
+// a << shift and the first threshold inside the bucket.
+__global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict__ sds,
+                                                    SeriesWork* __restrict__ works, uint2* __restrict__ rtab)
+{
+    __shared__ uint32_t es[RQA_MAX_K];
+    __shared__ uint32_t s_kp, s_shift;
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) es[r] = w.eps_bits[r];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t kp = sort_unique(es, K);
+        uint32_t sh = 0;
+        while (sh < 31 && (es[kp - 1] >> sh) - (es[0] >> sh) >= RHO_TABLE) ++sh;
+        s_kp = kp;
+        s_shift = sh;
+    }
+    __syncthreads();
+    const uint32_t kp = s_kp, sh = s_shift;
+    const uint32_t emin = es[0], emax = es[kp - 1];
+    for (uint32_t i = threadIdx.x; i < RQA_MAX_K; i += blockDim.x) w.esorted[i] = (i < kp) ? es[i] : 0xFFFFFFFFu;
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.dmap[r] = index_of(es, kp, w.eps_bits[r]);
+    for (uint32_t i = threadIdx.x; i <= RQA_MAX_K; i += blockDim.x) { w.hrho[i] = 0; w.hlam[i] = 0; }
+    if (threadIdx.x == 0) {
+        w.Kp = kp;
+        w.shift = sh;
+        w.emin = emin;
+        w.emax = emax;
+    }
+    const uint32_t a0 = emin >> sh, a1 = emax >> sh;
+    uint2* tab = rtab + (size_t)s * RHO_TABLE;
+    for (uint32_t idx = threadIdx.x; idx < RHO_TABLE; idx += blockDim.x) {
+        const uint32_t a = a0 + ((idx - a0) & (RHO_TABLE - 1));
+        uint2 e = make_uint2(0xFFFFFFFFu, 0u);
+        if (a <= a1) {
+            const uint64_t lo = (uint64_t)a << sh, hi = (uint64_t)(a + 1) << sh;
+            uint32_t below = 0, inside = 0;
+            for (uint32_t i = 0; i < kp; ++i) {
+                below += (uint64_t)es[i] < lo;
+                inside += ((uint64_t)es[i] >= lo) && ((uint64_t)es[i] < hi);
+            }
+            e.x = inside ? es[below] : 0xFFFFFFFFu;
+            e.y = (inside >= 2) ? (below | (inside << 16)) : below;
+        }
+        tab[idx] = e;
+    }
+}
+
+hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
+{
+    hipLaunchKernelGGL(k_sweep_prep, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.rtab);
+    return hipGetLastError();
+}
+
+hipError_t set_kernel_lds_limits(size_t max_dyn_lds)
+{
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < 6; ++v) {
+        for (int p = 1; p <= 3; ++p) {
+            hipError_t e = hipFuncSetAttribute((const void*)select_fn_pass(p, v),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+            if (e != hipSuccess) err = e;
+        }
+        for (int l = 0; l < 3; ++l) {
+            hipError_t e = hipFuncSetAttribute((const void*)sweep_fn(v * 3 + l),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+            if (e != hipSuccess) err = e;
+        }
+    }
+    return err;
+}
+
+}  // namespace rqa

@@ -1,0 +1,272 @@
+"""ctypes binding of librqa.so (include/rqa.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Series live in device memory as torch CUDA tensors
+(torch serves for device memory and streams); thresholds, targets and all
+results are host numpy arrays.  The functions carry the names of the C calls.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librqa.so")
+
+RQA_MAX_K = 128
+RQA_NORM_MAX = 0
+RQA_NORM_EUCLIDEAN = 1
+RQA_SEL_PLAIN = 0
+RQA_SEL_LEARNED = 1
+RQA_FULL_HIST = 2
+
+STATUS = {0: "RQA_OK", -1: "RQA_ERR_INVALID_ARG", -2: "RQA_ERR_TOO_SHORT",
+          -3: "RQA_ERR_NONFINITE", -4: "RQA_ERR_DEVICE", -5: "RQA_ERR_NOMEM",
+          -6: "RQA_ERR_UNSUPPORTED"}
+
+PHASES = ("select_pass1", "select_pass2", "select_pass3", "sweep", "other")
+
+
+class RqaError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class rqa_params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_uint32), ("tau", ctypes.c_uint32), ("norm", ctypes.c_uint32),
+                ("theiler", ctypes.c_uint32), ("lmin", ctypes.c_uint32)]
+
+
+_lib = None
+_u32, _u64, _i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+_vp = ctypes.c_void_p
+_fp = ctypes.POINTER(ctypes.c_float)
+_dp = ctypes.POINTER(ctypes.c_double)
+_up = ctypes.POINTER(ctypes.c_uint64)
+_pp = ctypes.POINTER(rqa_params)
+
+SIGNATURES = {
+    "rqa_create": (_i32, [ctypes.POINTER(_vp), _i32, _vp]),
+    "rqa_destroy": (None, [_vp]),
+    "rqa_select_thresholds": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, _u32, _fp, _up, _up]),
+    "rqa_det_curve": (_i32, [_vp, _vp, _u64, _pp, _fp, _u32, _u32, _up, _dp, _dp, _dp, _up, _u64]),
+    "rqa_run": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, _u32, _fp, _up, _up, _dp, _dp, _dp]),
+    "rqa_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up]),
+    "rqa_phase_times": (_i32, [_vp, _dp, _i32]),
+    "rqa_set_timing": (_i32, [_vp, _i32]),
+    "rqa_set_shape": (_i32, [_vp, _u32, _u32]),
+    "rqa_set_grid": (_i32, [_vp, _u32]),
+    "rqa_status_string": (ctypes.c_char_p, [_i32]),
+    "rqa_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load librqa.so; raise loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise RqaError(st, load().rqa_last_error().decode())
+
+
+def _params(p):
+    if isinstance(p, rqa_params):
+        return p
+    if isinstance(p, dict):
+        return rqa_params(p["m"], p["tau"], p["norm"], p.get("theiler", p.get("w", 1)), p["lmin"])
+    return rqa_params(*p)
+
+
+def _series_ptr(series):
+    """(device pointer, length) of a contiguous float32 CUDA tensor."""
+    import torch
+    if not isinstance(series, torch.Tensor) or not series.is_cuda:
+        raise TypeError("series must be a CUDA torch tensor (device memory)")
+    if series.dtype != torch.float32 or not series.is_contiguous():
+        raise TypeError("series must be contiguous float32")
+    return series.data_ptr(), series.numel()
+
+
+def _a(x, dtype):
+    return np.ascontiguousarray(x, dtype=dtype)
+
+
+def _p(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def rqa_status_string(status):
+    return load().rqa_status_string(status).decode()
+
+
+def rqa_last_error():
+    return load().rqa_last_error().decode()
+
+
+def rqa_create(device=0, stream=None):
+    """Context on `device`; `stream` is a torch.cuda.Stream, a raw hipStream_t
+    integer, or None for a context-owned stream."""
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    ctx = _vp()
+    _check(load().rqa_create(ctypes.byref(ctx), device, _vp(stream) if stream else None))
+    return ctx
+
+
+def rqa_destroy(ctx):
+    load().rqa_destroy(ctx)
+
+
+def rqa_set_timing(ctx, enable=True):
+    _check(load().rqa_set_timing(ctx, 1 if enable else 0))
+
+
+def rqa_phase_times(ctx):
+    out = np.zeros(len(PHASES), dtype=np.float64)
+    n = load().rqa_phase_times(ctx, _p(out, ctypes.c_double), len(PHASES))
+    return dict(zip(PHASES[:n], out[:n].tolist()))
+
+
+def rqa_set_shape(ctx, segment=0, chunk_tiles=0):
+    _check(load().rqa_set_shape(ctx, segment, chunk_tiles))
+
+
+def rqa_set_grid(ctx, workgroups=0):
+    _check(load().rqa_set_grid(ctx, workgroups))
+
+
+def rqa_select_thresholds(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
+    """Exact thresholds for the RR targets: (eps float32[K], k uint64[K],
+    count uint64[K])."""
+    ptr, n = _series_ptr(series)
+    rr = _a(rr, np.float64)
+    K = len(rr)
+    eps = np.zeros(K, np.float32)
+    k = np.zeros(K, np.uint64)
+    cnt = np.zeros(K, np.uint64)
+    prm = _params(params)
+    _check(load().rqa_select_thresholds(ctx, ptr, n, ctypes.byref(prm), _p(rr, ctypes.c_double), K, flags,
+                                        _p(eps, ctypes.c_float), _p(k, ctypes.c_uint64),
+                                        _p(cnt, ctypes.c_uint64)))
+    return eps, k, cnt
+
+
+def rqa_det_curve(ctx, series, params, eps, flags=0):
+    """RR and DET at the given thresholds: dict(count, rr, det, det_mean)."""
+    ptr, n = _series_ptr(series)
+    eps = _a(eps, np.float32)
+    K = len(eps)
+    cnt = np.zeros(K, np.uint64)
+    rr = np.zeros(K, np.float64)
+    det = np.zeros(K, np.float64)
+    dm = np.zeros(1, np.float64)
+    prm = _params(params)
+    _check(load().rqa_det_curve(ctx, ptr, n, ctypes.byref(prm), _p(eps, ctypes.c_float), K, flags,
+                                _p(cnt, ctypes.c_uint64), _p(rr, ctypes.c_double), _p(det, ctypes.c_double),
+                                _p(dm, ctypes.c_double), None, 0))
+    return {"count": cnt, "rr": rr, "det": det, "det_mean": float(dm[0])}
+
+
+def rqa_run(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
+    """Thresholds for the targets, then RR/DET at them: dict(eps, k, count,
+    rr, det, det_mean)."""
+    ptr, n = _series_ptr(series)
+    rrt = _a(rr, np.float64)
+    K = len(rrt)
+    eps = np.zeros(K, np.float32)
+    k = np.zeros(K, np.uint64)
+    cnt = np.zeros(K, np.uint64)
+    rro = np.zeros(K, np.float64)
+    det = np.zeros(K, np.float64)
+    dm = np.zeros(1, np.float64)
+    prm = _params(params)
+    _check(load().rqa_run(ctx, ptr, n, ctypes.byref(prm), _p(rrt, ctypes.c_double), K, flags,
+                          _p(eps, ctypes.c_float), _p(k, ctypes.c_uint64), _p(cnt, ctypes.c_uint64),
+                          _p(rro, ctypes.c_double), _p(det, ctypes.c_double), _p(dm, ctypes.c_double)))
+    return {"eps": eps, "k": k, "count": cnt, "rr": rro, "det": det, "det_mean": float(dm[0])}
+
+
+def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+    """S series back to back in one device tensor.  offsets: S+1 element
+    offsets; params: S parameter sets; rr: (S, K) targets.  Returns dict of
+    (S, K) arrays eps, rr, det, count and det_mean (S,)."""
+    ptr, _ = _series_ptr(concat)
+    offs = _a(offsets, np.uint64)
+    S = len(offs) - 1
+    rrt = _a(rr, np.float64)
+    if rrt.ndim != 2 or rrt.shape[0] != S:
+        raise ValueError("rr must have shape (S, K)")
+    K = rrt.shape[1]
+    prm = (rqa_params * S)(*[_params(p) for p in params])
+    eps = np.zeros((S, K), np.float32)
+    rro = np.zeros((S, K), np.float64)
+    det = np.zeros((S, K), np.float64)
+    cnt = np.zeros((S, K), np.uint64)
+    dm = np.zeros(S, np.float64)
+    _check(load().rqa_batch(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, _p(rrt, ctypes.c_double), K, flags,
+                            _p(eps, ctypes.c_float), _p(rro, ctypes.c_double), _p(det, ctypes.c_double),
+                            _p(dm, ctypes.c_double), _p(cnt, ctypes.c_uint64)))
+    return {"eps": eps, "rr": rro, "det": det, "det_mean": dm, "count": cnt}
+
+
+class Context:
+    """Owns an rqa context; methods mirror the C calls."""
+
+    def __init__(self, device=0, stream=None):
+        self.ctx = rqa_create(device, stream)
+
+    def close(self):
+        if self.ctx:
+            rqa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def select_thresholds(self, series, params, rr, flags=RQA_SEL_PLAIN):
+        return rqa_select_thresholds(self.ctx, series, params, rr, flags)
+
+    def det_curve(self, series, params, eps, flags=0):
+        return rqa_det_curve(self.ctx, series, params, eps, flags)
+
+    def run(self, series, params, rr, flags=RQA_SEL_PLAIN):
+        return rqa_run(self.ctx, series, params, rr, flags)
+
+    def batch(self, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+        return rqa_batch(self.ctx, concat, offsets, params, rr, flags)
+
+    def set_timing(self, enable=True):
+        rqa_set_timing(self.ctx, enable)
+
+    def phase_times(self):
+        return rqa_phase_times(self.ctx)
+
+    def set_shape(self, segment=0, chunk_tiles=0):
+        rqa_set_shape(self.ctx, segment, chunk_tiles)
+
+    def set_grid(self, workgroups=0):
+        rqa_set_grid(self.ctx, workgroups)

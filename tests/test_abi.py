@@ -1,0 +1,52 @@
+"""C-ABI checks that need no GPU: the library loads and exports every function
+the public header declares, with the documented status strings."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2208_09136_amd import rqa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rqa.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(rqa_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("rqa_create", "rqa_destroy", "rqa_select_thresholds", "rqa_det_curve",
+                 "rqa_batch", "rqa_run", "rqa_status_string", "rqa_last_error"):
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_library_exports(name):
+    lib = ctypes.CDLL(rqa.LIB_PATH)
+    assert hasattr(lib, name), name
+    assert name in rqa.SIGNATURES
+
+
+def test_status_strings():
+    assert rqa.rqa_status_string(0) == "ok"
+    assert rqa.rqa_status_string(-2) == "series too short"
+    assert rqa.rqa_status_string(-6) == "unsupported"
+    assert rqa.rqa_status_string(99) == "unknown status"
+
+
+def test_params_struct_layout():
+    assert ctypes.sizeof(rqa.rqa_params) == 20
+    p = rqa._params({"m": 3, "tau": 5, "norm": 1, "theiler": 1, "lmin": 2})
+    assert (p.m, p.tau, p.norm, p.theiler, p.lmin) == (3, 5, 1, 1, 2)
+
+
+def test_series_must_be_device_memory():
+    import numpy as np
+    with pytest.raises(TypeError):
+        rqa._series_ptr(np.zeros(10, np.float32))

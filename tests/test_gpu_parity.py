@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results (thresholds as bit patterns, ranks, counts) must match
+bit for bit; RR, DET and the averaged DET are ratios of those integers
+computed in double on both sides, so they must match exactly too."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "handbuilt_plots.json")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2208_09136_amd import rqa
+    c = rqa.Context(0, torch.cuda.current_stream())
+    yield c
+    c.close()
+
+
+def dev(y):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to("cuda:0")
+
+
+def prm(case):
+    return (case["m"], case["tau"], case["norm"], case["theiler"], case["lmin"])
+
+
+def assert_run_equal(got, want, label=""):
+    assert np.array_equal(got["eps"].view(np.uint32), want["eps"].view(np.uint32)), f"{label} eps"
+    assert np.array_equal(got["k"], want["k"]), f"{label} k"
+    assert np.array_equal(got["count"], want["count"]), f"{label} count"
+    assert np.array_equal(got["rr"], want["rr"]), f"{label} rr"
+    assert np.array_equal(got["det"], want["det"], equal_nan=True), f"{label} det"
+    assert got["det_mean"] == want["det_mean"] or (np.isnan(got["det_mean"]) and np.isnan(want["det_mean"])), label
+
+
+def oracle_run(case, rr=None):
+    rr = case["rr"] if rr is None else rr
+    return oracle.run(case["y"], case["m"], case["tau"], case["norm"], case["theiler"], case["lmin"], rr)
+
+
+def check_case(ctx, case, rr=None):
+    print(f"[parity] {case['name']} n={len(case['y'])} params={prm(case)}", flush=True)
+    rr = case["rr"] if rr is None else rr
+    got = ctx.run(dev(case["y"]), prm(case), rr)
+    want = oracle_run(case, rr)
+    assert_run_equal(got, want, case["name"])
+    return got
+
+
+# ---------------------------------------------------------------- workloads
+@pytest.mark.parametrize("seed", range(10))
+def test_small_logistic_max_norm(ctx, seed):
+    """Logistic r=4 + 10 dB noise, N=1000, m=1, max norm, K=20."""
+    check_case(ctx, synth.config_small(seed))
+
+
+@pytest.mark.parametrize("idx", range(15))
+def test_medium_systems_reduced_length(ctx, idx):
+    """The 15 series of the N=10^4 configuration, at N=2500 so the oracle's
+    sort path stays fast."""
+    check_case(ctx, synth.config_medium(n=2500)[idx])
+
+
+@pytest.mark.parametrize("idx", [0, 7, 12])
+def test_medium_systems_full_length(ctx, idx):
+    """Sine, logistic and Lorenz at N=10^4 (Euclidean; m=3, tau=5 for Lorenz)."""
+    check_case(ctx, synth.config_medium()[idx])
+
+
+def test_large_lorenz_sampled(ctx):
+    """N=10^5, m=3, tau=5, Euclidean, K=20 (4,998,950,055 pairs).  The oracle
+    cannot sort 5e9 keys in a test, so two sampled targets are checked through
+    properties that pin them at any size: the order-statistic bracket
+    #{key < eps} < k <= #{key <= eps} = count, and the line statistics at that
+    threshold recomputed by the oracle's plain per-threshold run-length pass."""
+    case = synth.config_large(which="lorenz")[0]
+    print(f"[parity] {case['name']} full size", flush=True)
+    got = ctx.run(dev(case["y"]), prm(case), case["rr"])
+    M = oracle.num_pairs(oracle.num_vectors(len(case["y"]), 3, 5), 1)
+    assert M == 4998950055
+    for r in (0, 19):
+        assert int(got["k"][r]) == oracle.rank(case["rr"][r], M)
+    sample = got["eps"][[0, 19]]
+    lt, le = oracle.count(case["y"], 3, 5, 1, 1, sample)
+    for i, r in enumerate((0, 19)):
+        assert lt[i] < got["k"][r] <= le[i]
+        assert le[i] == got["count"][r]
+    lin = oracle.lines(case["y"], 3, 5, 1, 1, 2, got["eps"][[19]])
+    assert lin["count"][0] == got["count"][19]
+    assert lin["det"][0] == got["det"][19]
+
+
+# ---------------------------------------------------------------- golden plots
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", golden()["cases"], ids=lambda c: c["name"])
+def test_handbuilt_plots(ctx, case):
+    y = np.array(case["y"], dtype=np.float32)
+    out = ctx.det_curve(dev(y), (case["m"], case["tau"], case["norm"], case["theiler"], case["lmin"]),
+                        [case["eps"]])
+    assert int(out["count"][0]) == case["count"]
+    assert out["rr"][0] == case["count"] / case["M"]
+    assert out["det"][0] == case["det_num"] / case["count"]
+
+
+def test_handbuilt_ranks(ctx):
+    g = golden()["ranks"]
+    y = np.array(g["y"], dtype=np.float32)
+    rr = [c["rr"] for c in g["cases"]]
+    eps, k, cnt = ctx.select_thresholds(dev(y), (g["m"], g["tau"], g["norm"], g["theiler"], 2), rr)
+    for i, c in enumerate(g["cases"]):
+        assert int(k[i]) == c["k"] and float(eps[i]) == c["eps"] and int(cnt[i]) == c["count"]
+
+
+# ---------------------------------------------------------------- parameters and edges
+@pytest.mark.parametrize("m,tau,norm,w,lmin", [
+    (1, 1, 0, 1, 2), (1, 1, 1, 1, 2), (3, 5, 1, 1, 2), (3, 5, 0, 1, 2), (2, 3, 1, 1, 2),
+    (4, 2, 0, 3, 2), (3, 3, 1, 7, 3), (1, 1, 0, 1, 1), (3, 5, 1, 1, 1), (2, 1, 1, 2, 5),
+    (1, 1, 1, 1, 16), (5, 1, 0, 1, 4), (3, 5, 1, 40, 2)])
+def test_parameter_grid(ctx, m, tau, norm, w, lmin):
+    y = synth.series("lorenz", 1500, 5.0, (7, m, tau, w))
+    case = {"name": f"grid_m{m}_tau{tau}_n{norm}_w{w}_l{lmin}", "y": y, "m": m, "tau": tau, "norm": norm,
+            "theiler": w, "lmin": lmin, "rr": np.array([0.003, 0.01, 0.05, 0.2, 0.5, 0.9])}
+    check_case(ctx, case)
+
+
+@pytest.mark.parametrize("shape", [(64, 1), (128, 3), (192, 2), (64, 4096), (4096, 1)])
+@pytest.mark.parametrize("n", [70, 130, 1000, 1023, 3001])
+def test_segment_and_chunk_shapes(ctx, shape, n):
+    """Ragged bands, segment halos and chunk boundaries: every launch shape
+    gives the oracle's result (a race canary as well)."""
+    ctx.set_shape(*shape)
+    try:
+        y = synth.series("logistic", n, 0.0, (8, n, 0, 0))
+        case = {"name": f"shape{shape}_n{n}", "y": y, "m": 2, "tau": 2, "norm": 1, "theiler": 1, "lmin": 2,
+                "rr": np.array(synth.RR_20)}
+        check_case(ctx, case)
+    finally:
+        ctx.set_shape(1024, 16)
+
+
+@pytest.mark.parametrize("grid", [1, 7, 4096])
+def test_more_workgroups_than_chunks(ctx, grid):
+    """Regression: persistent workgroups whose first ticket is already past
+    the end of the work queue must exit cleanly (they once dereferenced the
+    descriptor of a non-existent chunk).  grid=4096 on a one-chunk series makes
+    almost every workgroup start on a drained queue."""
+    ctx.set_grid(grid)
+    try:
+        check_case(ctx, synth.config_small(7))
+        case = synth.config_medium(n=3000)[12]
+        check_case(ctx, case)
+    finally:
+        ctx.set_grid(0)
+
+
+def test_unsorted_and_repeated_targets(ctx):
+    case = synth.config_small(4)
+    rr = np.array([0.2, 0.01, 0.05, 0.05, 1.0, 0.013, 0.2, 1e-9])
+    check_case(ctx, case, rr)
+
+
+def test_single_target_and_full_rate(ctx):
+    case = synth.config_small(5)
+    check_case(ctx, case, np.array([1.0]))
+    check_case(ctx, case, np.array([0.5]))
+
+
+def test_periodic_series_ties(ctx):
+    for n, P in [(600, 7), (1000, 37)]:
+        y = synth.periodic_integer(n, P)
+        Z = sum(n - d for d in range(P, n, P))
+        M = oracle.num_pairs(n, 1)
+        rr = np.array([Z / M * 0.3, Z / M * 0.9, 0.1, 0.5])
+        case = {"name": f"periodic_{n}_{P}", "y": y, "m": 1, "tau": 1, "norm": 0, "theiler": 1, "lmin": 2,
+                "rr": rr}
+        got = check_case(ctx, case)
+        assert got["eps"][0] == 0.0 and got["eps"][1] == 0.0
+
+
+def test_constant_series(ctx):
+    y = np.full(300, 2.5, dtype=np.float32)
+    case = {"name": "constant", "y": y, "m": 3, "tau": 2, "norm": 1, "theiler": 1, "lmin": 2,
+            "rr": np.array([0.01, 0.5, 1.0])}
+    got = check_case(ctx, case)
+    assert np.all(got["eps"] == 0.0)
+
+
+def test_minimal_series(ctx):
+    # nv - w = 1: exactly one pair
+    y = np.array([0.0, 1.0, 3.0, 7.0], dtype=np.float32)
+    case = {"name": "minimal", "y": y, "m": 2, "tau": 2, "norm": 1, "theiler": 1, "lmin": 2,
+            "rr": np.array([0.5, 1.0])}
+    got = check_case(ctx, case)
+    assert np.all(got["count"] == 1)
+
+
+def test_close_thresholds_share_buckets(ctx):
+    """Thresholds one ulp apart land in one bucket of the rank table and take
+    the slow comparison path."""
+    case = synth.config_small(6)
+    base = oracle.select(case["y"], 1, 1, 0, 1, [0.05])[0][0]
+    eps = [base]
+    for _ in range(6):
+        eps.append(np.nextafter(eps[-1], np.float32(np.inf), dtype=np.float32))
+    eps += [np.float32(base * 3), np.float32(0.0), np.float32(np.inf), np.float32(base * 0.5)]
+    eps = np.array(eps, dtype=np.float32)
+    got = ctx.det_curve(dev(case["y"]), prm(case), eps)
+    want = oracle.lines(case["y"], 1, 1, 0, 1, 2, eps)
+    assert np.array_equal(got["count"], want["count"])
+    assert np.array_equal(got["det"], want["det"], equal_nan=True)
+    assert np.array_equal(got["rr"], want["rr"])
+
+
+def test_det_curve_matches_selected(ctx):
+    case = synth.config_medium(n=2000)[13]
+    got = ctx.run(dev(case["y"]), prm(case), case["rr"])
+    dc = ctx.det_curve(dev(case["y"]), prm(case), got["eps"])
+    assert np.array_equal(dc["count"], got["count"])
+    assert np.array_equal(dc["det"], got["det"])
+    eps, k, cnt = ctx.select_thresholds(dev(case["y"]), prm(case), case["rr"])
+    assert np.array_equal(eps, got["eps"]) and np.array_equal(cnt, got["count"])
+
+
+def test_batch_equals_single(ctx):
+    cases = synth.config_batch(realisations=1)[::2][:12]
+    ys = [c["y"] for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(y) for y in ys])]).astype(np.uint64)
+    concat = dev(np.concatenate(ys))
+    rr = np.stack([c["rr"] for c in cases])
+    out = ctx.batch(concat, offs, [prm(c) for c in cases], rr)
+    for s, c in enumerate(cases):
+        single = ctx.run(dev(c["y"]), prm(c), c["rr"])
+        assert np.array_equal(out["eps"][s].view(np.uint32), single["eps"].view(np.uint32))
+        assert np.array_equal(out["count"][s], single["count"])
+        assert np.array_equal(out["det"][s], single["det"])
+        assert out["det_mean"][s] == single["det_mean"]
+    for s in (0, 5, 11):
+        assert_run_equal({**ctx.run(dev(cases[s]["y"]), prm(cases[s]), cases[s]["rr"])},
+                         oracle_run(cases[s]), cases[s]["name"])
+
+
+# ---------------------------------------------------------------- errors
+def test_error_paths(ctx):
+    from paper_2208_09136_amd.rqa import RqaError
+    y = synth.config_small(0)["y"]
+    good = (1, 1, 0, 1, 2)
+    bad = y.copy()
+    bad[500] = np.nan
+    with pytest.raises(RqaError) as e:
+        ctx.run(dev(bad), good, [0.1])
+    assert e.value.name == "RQA_ERR_NONFINITE"
+    bad[500] = np.inf
+    with pytest.raises(RqaError) as e:
+        ctx.det_curve(dev(bad), good, [0.1])
+    assert e.value.name == "RQA_ERR_NONFINITE"
+    with pytest.raises(RqaError) as e:
+        ctx.run(dev(y[:5]), (3, 2, 0, 1, 2), [0.1])
+    assert e.value.name == "RQA_ERR_TOO_SHORT"
+    for p in [(0, 1, 0, 1, 2), (1, 0, 0, 1, 2), (1, 1, 2, 1, 2), (1, 1, 0, 0, 2), (1, 1, 0, 1, 0)]:
+        with pytest.raises(RqaError) as e:
+            ctx.run(dev(y), p, [0.1])
+        assert e.value.name == "RQA_ERR_INVALID_ARG"
+    with pytest.raises(RqaError) as e:
+        ctx.run(dev(y), (1, 1, 0, 1, 17), [0.1])
+    assert e.value.name == "RQA_ERR_UNSUPPORTED"
+    for rr in ([], [0.0], [1.5], [float("nan")], [0.1] * 129):
+        with pytest.raises(RqaError) as e:
+            ctx.run(dev(y), good, rr)
+        assert e.value.name == "RQA_ERR_INVALID_ARG"
+    for eps in ([float("nan")], [-1.0]):
+        with pytest.raises(RqaError) as e:
+            ctx.det_curve(dev(y), good, eps)
+        assert e.value.name == "RQA_ERR_INVALID_ARG"
+    with pytest.raises(RqaError) as e:
+        ctx.run(dev(y), good, [0.1], flags=2)
+    assert e.value.name == "RQA_ERR_UNSUPPORTED"
+    # the context still works after errors
+    check_case(ctx, synth.config_small(0))
