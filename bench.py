@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the averaged-RQA hot path on one MI355X.
+
+A step is one whole pass of the path over the large workload: exact
+threshold selection for K = 20 target recurrence rates (three radix passes)
+and the line sweep giving RR, DET and the averaged DET, for both large series
+(Lorenz-x + 0 dB noise and logistic r=4 + -10 dB noise, N = 10^5, m = 3,
+tau = 5, Euclidean norm, Theiler window 1, l_min = 2), as one rqa_batch call.
+Inputs are resident in device memory before the timed region.
+
+value = pairs x thresholds per second over the timed steps, where pairs are
+the M = (Nv-1) Nv / 2 upper-triangle pairs each series has.
+
+Also reported (outside the timed steps): the 600-series batched ensemble
+(series/s, batched against one call per series), per-phase device times from
+HIP events on the library's stream, the roofline of the dominant kernel and
+the CPU oracle timed on a bounded sample.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "recurrence cells x thresholds/s at N=1e5, K=20 (+ batched series/s), % VALU peak"
+K = 20
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, in lane-ops/s.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU lane-ops of one key for (norm, m): the m subtractions, the
+# m |.| or squares and the m-1 max or add steps.
+def key_ops(norm, m):
+    return 3 * m - 1
+
+
+def cells_of(case):
+    nv = len(case["y"]) - (case["m"] - 1) * case["tau"]
+    a = nv - case["theiler"]
+    return a * (a + 1) // 2
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 600-series ensemble")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=10_000,
+                    help="prefix length of the Lorenz series the oracle is timed on")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the path shards by diagonal "
+                                   "bands across GPUs in design only", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2208_09136_amd import rqa
+
+    cases = synth.config_large()
+    prm = [(c["m"], c["tau"], c["norm"], c["theiler"], c["lmin"]) for c in cases]
+    ys = [c["y"] for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(y) for y in ys])]).astype(np.uint64)
+    dev = torch.device("cuda:0")
+    concat = torch.from_numpy(np.concatenate(ys)).to(dev)
+    rr = np.stack([c["rr"] for c in cases])
+    cells = [cells_of(c) for c in cases]
+    cell_thr = sum(cells) * K
+
+    stream = torch.cuda.current_stream()
+    ctx = rqa.Context(0, stream)
+    ctx.set_timing(True)
+
+    ref = None
+    for _ in range(args.warmup):
+        ref = ctx.batch(concat, offs, prm, rr)
+    torch.cuda.synchronize()
+    phases = np.zeros(len(rqa.PHASES))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.batch(concat, offs, prm, rr)
+        phases += np.array([ctx.phase_times()[p] for p in rqa.PHASES])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if ref is not None:
+        assert np.array_equal(ref["det_mean"], out["det_mean"]), "results changed between steps"
+    sec = (t1 - t0) / args.steps
+    value = cell_thr / sec
+    ph = dict(zip(rqa.PHASES, (phases / args.steps).tolist()))
+
+    # roofline of the dominant kernel: the phase with the largest device time;
+    # one launch per phase per step.  Algorithmic lane-ops per pair: the key,
+    # then per selection pass 2 (bucket of the key, one count), per sweep 2 per
+    # threshold (one comparison, one run-length update).
+    kops = key_ops(1, 3)
+    per_launch_ops = {
+        "select_pass1": sum(cells) * (kops + 2),
+        "select_pass2": sum(cells) * (kops + 2),
+        "select_pass3": sum(cells) * (kops + 2),
+        "sweep": sum(cells) * (kops + 2 * K),
+    }
+    dom = max(per_launch_ops, key=lambda p: ph[p])
+    achieved = per_launch_ops[dom] / (ph[dom] * 1e-3)
+    step_ops = sum(per_launch_ops.values())
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "algorithmic_ops_per_launch": per_launch_ops[dom], "launch_ms": ph[dom]}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "cell-thresholds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2 series x N=1e5 (Lorenz-x 0 dB, logistic r=4 -10 dB), m=3, tau=5, "
+                               "Euclidean, Theiler 1, l_min 2, K=20 RR 0.01..0.20; select + sweep",
+                   "pairs_per_series": cells, "K": K, "global_batch": len(cases), "seq_len": 100_000,
+                   "parallelism": "single-gpu"},
+        "phases_ms": ph,
+        "valu_peak_frac": step_ops / sec / VALU_PEAK,
+        "roofline": roofline,
+        "det_mean": out["det_mean"].tolist(),
+    }
+
+    if not args.no_batch:
+        result["batched"] = bench_batch(ctx, torch, rqa)
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(cases[0], args.cpu_sample)
+
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def bench_batch(ctx, torch, rqa, reps=3):
+    """The 600-series ensemble (3 systems x 10 SNRs x 20 realisations, lengths
+    log-uniform in [100, 2e4]) in one rqa_batch call, against one rqa_run call
+    per series on the same GPU."""
+    cases = synth.config_batch()
+    ys = [c["y"] for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(y) for y in ys])]).astype(np.uint64)
+    concat = torch.from_numpy(np.concatenate(ys)).to("cuda:0")
+    prm = [(c["m"], c["tau"], c["norm"], c["theiler"], c["lmin"]) for c in cases]
+    rr = np.stack([c["rr"] for c in cases])
+    cells = sum(cells_of(c) for c in cases)
+    ctx.batch(concat, offs, prm, rr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = ctx.batch(concat, offs, prm, rr)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    singles = [torch.from_numpy(y).to("cuda:0") for y in ys]
+    for s in range(3):
+        ctx.run(singles[s], prm[s], rr[s])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for s in range(len(cases)):
+        o = ctx.run(singles[s], prm[s], rr[s])
+        same &= bool(np.array_equal(o["det"], out["det"][s]))
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return {"series": len(cases), "pairs": int(cells), "ms": tb * 1e3, "series_per_s": len(cases) / tb,
+            "cell_thresholds_per_s": cells * K / tb, "single_calls_ms": ts * 1e3,
+            "single_series_per_s": len(cases) / ts, "batched_over_single": ts / tb,
+            "equal_to_single": same}
+
+
+def cpu_baseline(case, n_sample):
+    """The CPU oracle (plain C, OpenMP over diagonals) on a prefix of the Lorenz
+    series with the same parameters: exact selection (sort path) and the
+    per-threshold run-length pass."""
+    import oracle
+    y = case["y"][:n_sample]
+    sub = dict(case, y=y)
+    t0 = time.perf_counter()
+    oracle.run(y, case["m"], case["tau"], case["norm"], case["theiler"], case["lmin"], case["rr"])
+    dt = time.perf_counter() - t0
+    cells = cells_of(sub)
+    return {"value": cells * K / dt, "unit": "cell-thresholds/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": dt,
+            "sample": f"first {n_sample} samples of the Lorenz-x 0 dB series, m=3, tau=5, Euclidean, "
+                      f"K=20: {cells} pairs, selection + lines"}
+
+
+if __name__ == "__main__":
+    main()
