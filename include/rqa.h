@@ -145,10 +145,48 @@ int rqa_phase_times(rqa_ctx *ctx, double *times_out, int n_out);
 /* Enable (1) or disable (0) per-phase HIP-event timing on the context. */
 rqa_status rqa_set_timing(rqa_ctx *ctx, int enable);
 
-/* Kernel launch shape: segment length along a diagonal (multiple of 64,
- * 64..65536) and tiles per work chunk (1..4096).  0 keeps the current value.
- * Applies to later calls on this context. */
+/* Kernel launch shape overrides for later calls on this context: segment
+ * length along a diagonal (a multiple of 64, at most 65536) and tiles per
+ * work chunk (at most 4096).  0 selects automatic: the autotuned table of the
+ * context where it has the size bucket, otherwise about 16 segments per
+ * series (64..1024) and 8 tiles per chunk.  Shapes never change results. */
 rqa_status rqa_set_shape(rqa_ctx *ctx, uint32_t segment, uint32_t chunk_tiles);
+
+/* Launch-shape autotuner (batched persistent launch of the workload
+ * configurations).  Times the whole path (rqa_run) on the given series for
+ * candidate segment lengths (powers of two from 64 to 4096) and chunk sizes
+ * {2, 8, 32}, and records the fastest in the context's table under the size
+ * bucket (log2 of the number of vectors, norm, embedding and line class, K up
+ * to 32 or beyond).  segment_out/chunk_tiles_out (or NULL) receive it.
+ * Arguments as in rqa_run. */
+rqa_status rqa_autotune(rqa_ctx *ctx, const float *series_dev, uint64_t n, const rqa_params *p,
+                        const double *rr, uint32_t K, uint32_t *segment_out, uint32_t *chunk_tiles_out);
+
+/* Autotuner for rqa_batch: tunes the segment length of every size bucket
+ * present in the batch (on up to 64 of its series), then the chunk size of
+ * the whole batch, and records them for later multi-series calls.
+ * Arguments as in rqa_batch. */
+rqa_status rqa_autotune_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
+                              const rqa_params *p, const double *rr, uint32_t K, uint32_t *chunk_tiles_out);
+
+/* Distance sketch of S series (the input of the threshold-bracket network;
+ * an extension of the paper's method).  For series s, RQA_SKETCH_PAIRS pairs
+ * are drawn with the SplitMix64 output function of counter q on stream
+ * seed + s (pair index = output mod M, pairs numbered diagonal by diagonal);
+ * their keys give the median `scale` (bit pattern, scale_out[s]) and the
+ * counts of clamp(((bits - scale) >> 21) + 32, 0, 63) divided by
+ * RQA_SKETCH_PAIRS as features 0..63; feature 64 is log2(n)/16 and feature
+ * 65 is m/4.  features_out: S*RQA_SKETCH_FEATURES floats (host).  Series as in
+ * rqa_batch. */
+#define RQA_SKETCH_PAIRS 4096
+#define RQA_SKETCH_FEATURES 66
+rqa_status rqa_sketch_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
+                            const rqa_params *p, uint64_t seed, float *features_out, uint32_t *scale_out);
+
+/* Save / load the context's autotuned table as JSON (path: host string).
+ * Loading replaces the table; a malformed file leaves it unchanged. */
+rqa_status rqa_tune_save(rqa_ctx *ctx, const char *path);
+rqa_status rqa_tune_load(rqa_ctx *ctx, const char *path);
 
 /* Number of persistent workgroups of every counting launch (selection passes
  * and sweep).  0 (the default) sizes each launch to one full set of resident

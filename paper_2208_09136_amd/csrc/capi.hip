@@ -12,10 +12,14 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <chrono>
 #include <cstring>
+#include <map>
+#include <string>
 #include <vector>
 
 #include "internal.h"
+#include "mlp.h"
 
 using namespace rqa;
 
@@ -41,6 +45,22 @@ rqa_status fail(rqa_status st, const char* fmt, ...)
 
 enum Phase { PH_P1 = 0, PH_P2 = 1, PH_P3 = 2, PH_SWEEP = 3, PH_OTHER = 4, PH_N = 5 };
 
+// Size bucket of the autotuner: log2 of the number of vectors, the kernel
+// variant (norm, embedding class, line class) and K up to 32 or beyond.  The
+// bucket with nvlog2 = -1 holds the chunk size of multi-series calls.
+struct TuneKey {
+    int nvlog2, variant, kcls;
+    bool operator<(const TuneKey& o) const
+    {
+        if (nvlog2 != o.nvlog2) return nvlog2 < o.nvlog2;
+        if (variant != o.variant) return variant < o.variant;
+        return kcls < o.kcls;
+    }
+};
+struct Shape {
+    uint32_t seg, chunk;
+};
+
 }  // namespace
 
 struct rqa_ctx {
@@ -49,9 +69,18 @@ struct rqa_ctx {
     bool own_stream = false;
     int num_cu = 256;
     size_t max_lds = 65536;
-    uint32_t seg = 1024;
-    uint32_t chunk_tiles = 16;
-    uint32_t grid = 0;  // 0: automatic
+    uint32_t seg = 0;          // segment length override (0: tuned table or heuristic)
+    uint32_t chunk_tiles = 0;  // chunk size override (0: tuned table or heuristic)
+    uint32_t grid = 0;         // workgroups per launch override (0: automatic)
+    std::map<TuneKey, Shape> tune;  // autotuned shapes per size bucket
+    // threshold-bracket network: device params | grad | Adam m | Adam v
+    float* mlp = nullptr;
+    float* mlp_acts = nullptr;   // activations for up to mlp_cap rows
+    uint32_t mlp_cap = 0;
+    float* mlp_partial = nullptr;
+    uint64_t adam_t = 0;
+    bool has_model = false;
+    float bracket_delta[MLP_OUT] = {};  // calibrated half-widths of the bracket (offset units)
     // device pool
     void* pool = nullptr;
     size_t pool_bytes = 0;
@@ -116,6 +145,46 @@ rqa_status check_eps(float e, uint32_t* bits)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+int log2_floor(uint64_t v)
+{
+    int l = 0;
+    while (v >>= 1) ++l;
+    return l;
+}
+
+TuneKey tune_key(uint64_t nv, const rqa_params& p, uint32_t K)
+{
+    return {log2_floor(nv), variant_of(p.norm, p.m, p.tau, p.lmin), K <= 32 ? 0 : 1};
+}
+
+// Default segment length when nothing is tuned: about 16 segments per series,
+// a power of two between 64 and 1024.
+uint32_t default_segment(uint64_t L0)
+{
+    uint64_t t = 64;
+    while (t * 2 <= L0 / 16 && t < 1024) t *= 2;
+    return (uint32_t)t;
+}
+
+constexpr uint32_t DEFAULT_CHUNK = 8;
+
+uint32_t segment_for(const rqa_ctx* c, uint64_t nv, const rqa_params& p, uint32_t K)
+{
+    if (c->seg) return c->seg;
+    auto it = c->tune.find(tune_key(nv, p, K));
+    if (it != c->tune.end()) return it->second.seg;
+    return default_segment(nv - p.theiler);
+}
+
+uint32_t chunk_for(const rqa_ctx* c, uint32_t S, uint64_t nv0, const rqa_params& p0, uint32_t K)
+{
+    if (c->chunk_tiles) return c->chunk_tiles;
+    const TuneKey key = S == 1 ? tune_key(nv0, p0, K) : TuneKey{-1, 0, K <= 32 ? 0 : 1};
+    auto it = c->tune.find(key);
+    if (it != c->tune.end()) return it->second.chunk;
+    return DEFAULT_CHUNK;
+}
+
 rqa_status ensure_pool(rqa_ctx* c, size_t bytes)
 {
     if (c->pool_bytes >= bytes) return RQA_OK;
@@ -176,13 +245,14 @@ struct Timer {
     }
 };
 
-enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3 };
+enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3, MODE_SKETCH = 4 };
 
 struct Job {
     std::vector<Series> series;
     const float* base = nullptr;     // device
     uint32_t K = 0;
     int mode = MODE_BOTH;
+    uint64_t seed = 0;               // sketch stream of series 0 (series s uses seed + s)
     std::vector<uint64_t> k;         // S*K, selection targets
     std::vector<uint32_t> eps_bits;  // S*K, sweep-only thresholds
     // results
@@ -190,6 +260,8 @@ struct Job {
     std::vector<uint64_t> kout, count_sel, count;
     std::vector<double> rr, det, det_mean;
     std::vector<uint64_t> M;
+    std::vector<float> features;     // S*SKETCH_FEATURES (sketch mode)
+    std::vector<uint32_t> scale;     // S (sketch mode)
 };
 
 // Runs selection and/or sweep for every series of the job.
@@ -197,7 +269,11 @@ rqa_status run_job(rqa_ctx* c, Job& job)
 {
     const uint32_t S = (uint32_t)job.series.size();
     const uint32_t K = job.K;
-    const uint32_t T = c->seg, CT = c->chunk_tiles;
+    uint32_t CT;
+    {
+        const Series& z0 = job.series[0];
+        CT = chunk_for(c, S, z0.n - (uint64_t)(z0.p.m - 1) * z0.p.tau, z0.p, K);
+    }
 
     // descriptors, ordered by kernel variant so each launch sees a contiguous range
     std::vector<uint32_t> order(S);
@@ -210,13 +286,15 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         rqa_status st = check_params(&z.p, z.n, &nv, &M);
         if (st) return st;
         job.M[s] = M;
-        sel_var[s] = select_variant_of(z.p.norm, z.p.m);
-        swp_var[s] = variant_of(z.p.norm, z.p.m, z.p.lmin);
+        sel_var[s] = select_variant_of(z.p.norm, z.p.m, z.p.tau);
+        swp_var[s] = variant_of(z.p.norm, z.p.m, z.p.tau, z.p.lmin);
         order[s] = s;
     }
+    // largest series first inside a variant: their chunks leave the queue first
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
         if (swp_var[a] != swp_var[b]) return swp_var[a] < swp_var[b];
-        return job.series[a].p.lmin < job.series[b].p.lmin;
+        if (job.series[a].p.lmin != job.series[b].p.lmin) return job.series[a].p.lmin < job.series[b].p.lmin;
+        return job.M[a] > job.M[b];
     });
     // groups: consecutive device series sharing the sweep variant (and lmin for the generic one)
     struct Group { uint32_t begin, end; int sel, swp; uint32_t nchunks; };
@@ -233,6 +311,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
         const uint64_t L0 = nv - z.p.theiler;
         SeriesDesc& d = sd[i];
+        const uint32_t T = segment_for(c, nv, z.p, K);
         d.y = job.base + z.offset;
         d.n = (uint32_t)z.n;
         d.nv = (uint32_t)nv;
@@ -253,6 +332,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         d.nchunks = (uint32_t)((ntiles + CT - 1) / CT);
         d.chunk_begin = g.nchunks;  // chunk numbering restarts in every group
         d.variant = (uint32_t)swp_var[s];
+        d.seed = job.seed + s;
+        d.f_logn = (float)(std::log2((double)z.n) / 16.0);
+        d.f_m = (float)((double)z.p.m / 4.0);
         g.nchunks += d.nchunks;
         maxn = std::max<uint32_t>(maxn, (uint32_t)z.n);
     }
@@ -270,6 +352,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
     const size_t o_rt = carve(sizeof(uint2) * S * RHO_TABLE);
+    const size_t o_feat = (job.mode & MODE_SKETCH) ? carve(sizeof(float) * S * SKETCH_FEATURES) : 0;
     rqa_status st = ensure_pool(c, off);
     if (st) return st;
     char* pool = (char*)c->pool;
@@ -288,20 +371,22 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     all.chunk_tiles = CT;
     all.nchunks = 0;
 
-    // host staging: descriptors + work (in), work (out)
+    // host staging: descriptors + work (in), work (out), sketch features (out)
     const size_t hs_sd = sizeof(SeriesDesc) * S, hs_work = sizeof(SeriesWork) * S;
-    st = ensure_host(c, hs_sd + 2 * hs_work);
+    const size_t hs_feat = (job.mode & MODE_SKETCH) ? sizeof(float) * S * SKETCH_FEATURES : 0;
+    st = ensure_host(c, hs_sd + 2 * hs_work + hs_feat);
     if (st) return st;
     SeriesDesc* h_sd = (SeriesDesc*)c->host;
     SeriesWork* h_work = (SeriesWork*)((char*)c->host + hs_sd);
     SeriesWork* h_out = (SeriesWork*)((char*)c->host + hs_sd + hs_work);
+    float* h_feat = (float*)((char*)c->host + hs_sd + 2 * hs_work);
     std::memcpy(h_sd, sd.data(), hs_sd);
     std::memset(h_work, 0, hs_work);
     for (uint32_t i = 0; i < S; ++i) {
         const uint32_t s = order[i];
         for (uint32_t r = 0; r < K; ++r) {
             if (job.mode & MODE_SELECT) h_work[i].k[r] = job.k[(size_t)s * K + r];
-            else h_work[i].eps_bits[r] = job.eps_bits[(size_t)s * K + r];
+            else if (job.mode & MODE_SWEEP) h_work[i].eps_bits[r] = job.eps_bits[(size_t)s * K + r];
         }
     }
 
@@ -312,6 +397,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     HIP_TRY(hipMemcpyAsync(all.work, h_work, hs_work, hipMemcpyHostToDevice, sm));
     HIP_TRY(launch_zero(sm, pool + o_tick, zero_end - o_tick));
     HIP_TRY(launch_check_finite(sm, all, maxn));
+    if (job.mode & MODE_SKETCH) HIP_TRY(launch_sketch(sm, all, (float*)(pool + o_feat), nullptr));
     HIP_TRY(tm.end());
 
     auto view = [&](const Group& g) {
@@ -342,15 +428,17 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             HIP_TRY(tm.begin(pass - 1));
             for (const Group& g : groups) {
                 DevBufs v = view(g);
-                uint32_t block = pass == 1 ? 256 : 1024;
+                const uint32_t block = 512;
                 uint32_t G = 1, ngroups = 1;
-                if (pass > 1) {
-                    const size_t fixed = select_lds_bytes(pass, K, 0);
-                    const size_t per = pass == 2 ? SEL_N2 * 4 : SEL_N3 * 4;
+                if (pass == 2) {
+                    // pass-2 slots that fit the LDS next to the 4 KB bucket table
+                    const size_t fixed = select_lds_bytes(2, K, 0);
                     const size_t room = c->max_lds > fixed ? c->max_lds - fixed : 0;
-                    G = (uint32_t)std::min<size_t>(K, room / per);
-                    if (G == 0) return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass %d", K, pass);
+                    G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4));
+                    if (G == 0) return fail(RQA_ERR_UNSUPPORTED, "pass 2 does not fit the LDS");
                     ngroups = (K + G - 1) / G;
+                } else if (pass == 3 && select_lds_bytes(3, K, 0) > c->max_lds) {
+                    return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass 3", K);
                 }
                 const size_t lds = select_lds_bytes(pass, K, G);
                 const int per_cu = select_blocks_per_cu(pass, g.sel, block, lds);
@@ -385,6 +473,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         HIP_TRY(tm.end());
     }
     HIP_TRY(hipMemcpyAsync(h_out, all.work, hs_work, hipMemcpyDeviceToHost, sm));
+    if (hs_feat) HIP_TRY(hipMemcpyAsync(h_feat, pool + o_feat, hs_feat, hipMemcpyDeviceToHost, sm));
     HIP_TRY(hipStreamSynchronize(sm));
     tm.collect();
 
@@ -396,11 +485,20 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     job.rr.assign((size_t)S * K, 0.0);
     job.det.assign((size_t)S * K, 0.0);
     job.det_mean.assign(S, 0.0);
+    if (job.mode & MODE_SKETCH) {
+        job.features.assign((size_t)S * SKETCH_FEATURES, 0.f);
+        job.scale.assign(S, 0);
+    }
     for (uint32_t i = 0; i < S; ++i) {
         const uint32_t s = order[i];
         const SeriesWork& w = h_out[i];
         if (w.nonfinite) return fail(RQA_ERR_NONFINITE, "series %u holds a NaN or infinite sample", s);
         if (w.status) return fail(RQA_ERR_DEVICE, "selection of series %u is inconsistent (code %u)", s, w.status);
+        if (job.mode & MODE_SKETCH) {
+            std::memcpy(&job.features[(size_t)s * SKETCH_FEATURES], h_feat + (size_t)i * SKETCH_FEATURES,
+                        sizeof(float) * SKETCH_FEATURES);
+            job.scale[s] = w.scale;
+        }
         for (uint32_t r = 0; r < K; ++r) {
             float e;
             std::memcpy(&e, &w.eps_bits[r], 4);
@@ -455,6 +553,26 @@ rqa_status check_flags_select(uint32_t flags)
     return RQA_OK;
 }
 
+rqa_status single_job_setup(rqa_ctx* c, Job& job, const float* series, uint64_t n, const rqa_params* p,
+                            const double* rr, uint32_t K)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (!series) return fail(RQA_ERR_INVALID_ARG, "series pointer is NULL");
+    if ((st = check_k(K))) return st;
+    uint64_t nv, M;
+    if ((st = check_params(p, n, &nv, &M))) return st;
+    if (!rr) return fail(RQA_ERR_INVALID_ARG, "rr is NULL");
+    job.series.push_back({0, n, *p});
+    job.base = series;
+    job.K = K;
+    job.mode = MODE_BOTH;
+    job.k.resize(K);
+    for (uint32_t r = 0; r < K; ++r)
+        if ((st = target_rank(rr[r], M, &job.k[r]))) return st;
+    return RQA_OK;
+}
+
 rqa_status single_job(rqa_ctx* c, Job& job, const float* series, uint64_t n, const rqa_params* p,
                       const double* rr, const float* eps, uint32_t K, int mode)
 {
@@ -480,6 +598,130 @@ rqa_status single_job(rqa_ctx* c, Job& job, const float* series, uint64_t n, con
             if ((st = check_eps(eps[r], &job.eps_bits[r]))) return st;
     }
     return run_job(c, job);
+}
+
+rqa_status build_batch_job(Job& job, uint32_t S, const float* concat, const uint64_t* offsets, const rqa_params* p,
+                           const double* rr, uint32_t K)
+{
+    rqa_status st;
+    if ((st = check_k(K))) return st;
+    if (S == 0 || !concat || !offsets || !p || !rr) return fail(RQA_ERR_INVALID_ARG, "S is 0 or a required pointer is NULL");
+    job.base = concat;
+    job.K = K;
+    job.mode = MODE_BOTH;
+    job.k.resize((size_t)S * K);
+    for (uint32_t s = 0; s < S; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(RQA_ERR_INVALID_ARG, "offsets decrease at series %u", s);
+        const uint64_t n = offsets[s + 1] - offsets[s];
+        uint64_t nv, M;
+        if ((st = check_params(&p[s], n, &nv, &M))) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "series %u: %s", s, g_err);
+            return fail(st, "%s", msg);
+        }
+        job.series.push_back({offsets[s], n, p[s]});
+        for (uint32_t r = 0; r < K; ++r)
+            if ((st = target_rank(rr[(size_t)s * K + r], M, &job.k[(size_t)s * K + r]))) return st;
+    }
+    return RQA_OK;
+}
+
+// Best host wall time (ms) of `reps` calls of the job; each call synchronises.
+rqa_status time_job(rqa_ctx* c, Job& job, int reps, double* best)
+{
+    *best = 1e300;
+    for (int i = 0; i < reps; ++i) {
+        Job j = job;
+        const auto t0 = std::chrono::steady_clock::now();
+        rqa_status st = run_job(c, j);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st) return st;
+        *best = std::min(*best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    return RQA_OK;
+}
+
+// Candidate segment lengths: powers of two from 64 up to the longest diagonal
+// (at most 4096).
+std::vector<uint32_t> segment_candidates(uint64_t L0)
+{
+    std::vector<uint32_t> v;
+    for (uint32_t t = 64; t <= 4096; t *= 2) {
+        v.push_back(t);
+        if (t >= L0) break;
+    }
+    return v;
+}
+
+const uint32_t CHUNK_CANDIDATES[] = {2, 8, 32};
+
+// Tunes the segment length of each size bucket present in the job (on up to
+// 64 of its series, chunk size at the default) and then the chunk size of the
+// whole job; records everything in the context's table.
+rqa_status tune_job(rqa_ctx* c, Job& job, uint32_t* seg_out, uint32_t* chunk_out)
+{
+    const uint32_t save_seg = c->seg, save_chunk = c->chunk_tiles;
+    const uint32_t K = job.K;
+    std::map<TuneKey, std::vector<uint32_t>> buckets;
+    uint64_t maxL0 = 0;
+    for (uint32_t s = 0; s < (uint32_t)job.series.size(); ++s) {
+        const Series& z = job.series[s];
+        const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
+        buckets[tune_key(nv, z.p, K)].push_back(s);
+        maxL0 = std::max<uint64_t>(maxL0, nv - z.p.theiler);
+    }
+    rqa_status st = RQA_OK;
+    uint32_t last_seg = 0;
+    for (auto& kv : buckets) {
+        Job sub;
+        sub.base = job.base;
+        sub.K = K;
+        sub.mode = job.mode;
+        uint64_t L0 = 0;
+        for (size_t i = 0; i < kv.second.size() && i < 64; ++i) {
+            const uint32_t s = kv.second[i];
+            sub.series.push_back(job.series[s]);
+            sub.k.insert(sub.k.end(), job.k.begin() + (size_t)s * K, job.k.begin() + (size_t)(s + 1) * K);
+            const Series& z = job.series[s];
+            L0 = std::max<uint64_t>(L0, z.n - (uint64_t)(z.p.m - 1) * z.p.tau - z.p.theiler);
+        }
+        double best = 1e300;
+        uint32_t best_seg = 64;
+        c->chunk_tiles = DEFAULT_CHUNK;
+        for (uint32_t T : segment_candidates(L0)) {
+            c->seg = T;
+            double ms;
+            if ((st = time_job(c, sub, 2, &ms))) break;
+            if (ms < best) { best = ms; best_seg = T; }
+        }
+        if (st) break;
+        c->tune[kv.first] = {best_seg, DEFAULT_CHUNK};
+        last_seg = best_seg;
+    }
+    uint32_t best_chunk = DEFAULT_CHUNK;
+    if (!st) {
+        c->seg = 0;  // the table just filled
+        double best = 1e300;
+        for (uint32_t CT : CHUNK_CANDIDATES) {
+            c->chunk_tiles = CT;
+            double ms;
+            if ((st = time_job(c, job, 2, &ms))) break;
+            if (ms < best) { best = ms; best_chunk = CT; }
+        }
+    }
+    c->seg = save_seg;
+    c->chunk_tiles = save_chunk;
+    if (st) return st;
+    if (job.series.size() == 1) {
+        auto& e = c->tune[buckets.begin()->first];
+        e.chunk = best_chunk;
+    } else {
+        c->tune[TuneKey{-1, 0, K <= 32 ? 0 : 1}] = {0, best_chunk};
+    }
+    if (seg_out) *seg_out = job.series.size() == 1 ? last_seg : 0;
+    if (chunk_out) *chunk_out = best_chunk;
+    (void)maxL0;
+    return RQA_OK;
 }
 
 }  // namespace
@@ -528,6 +770,9 @@ void rqa_destroy(rqa_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->pool) (void)hipFree(c->pool);
     if (c->host) (void)hipHostFree(c->host);
+    if (c->mlp) (void)hipFree(c->mlp);
+    if (c->mlp_acts) (void)hipFree(c->mlp_acts);
+    if (c->mlp_partial) (void)hipFree(c->mlp_partial);
     if (c->ev_ready)
         for (auto& e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -557,15 +802,11 @@ int rqa_phase_times(rqa_ctx* c, double* out, int n)
 rqa_status rqa_set_shape(rqa_ctx* c, uint32_t segment, uint32_t chunk_tiles)
 {
     if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
-    if (segment) {
-        if (segment % TILE_W || segment < TILE_W || segment > 65536)
-            return fail(RQA_ERR_INVALID_ARG, "segment %u must be a multiple of 64 in 64..65536", segment);
-        c->seg = segment;
-    }
-    if (chunk_tiles) {
-        if (chunk_tiles > 4096) return fail(RQA_ERR_INVALID_ARG, "chunk_tiles %u > 4096", chunk_tiles);
-        c->chunk_tiles = chunk_tiles;
-    }
+    if (segment && (segment % TILE_W || segment > 65536))
+        return fail(RQA_ERR_INVALID_ARG, "segment %u must be a multiple of 64 in 64..65536", segment);
+    if (chunk_tiles > 4096) return fail(RQA_ERR_INVALID_ARG, "chunk_tiles %u > 4096", chunk_tiles);
+    c->seg = segment;
+    c->chunk_tiles = chunk_tiles;
     return RQA_OK;
 }
 
@@ -641,27 +882,9 @@ rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t
     rqa_status st = check_ctx(c);
     if (st) return st;
     if ((st = check_flags_select(flags))) return st;
-    if ((st = check_k(K))) return st;
-    if (S == 0 || !concat || !offsets || !p || !rr || !eps_out || !rr_out || !det_out || !det_mean_out)
-        return fail(RQA_ERR_INVALID_ARG, "S is 0 or a required pointer is NULL");
+    if (!eps_out || !rr_out || !det_out || !det_mean_out) return fail(RQA_ERR_INVALID_ARG, "an output is NULL");
     Job job;
-    job.base = concat;
-    job.K = K;
-    job.mode = MODE_BOTH;
-    job.k.resize((size_t)S * K);
-    for (uint32_t s = 0; s < S; ++s) {
-        if (offsets[s + 1] < offsets[s]) return fail(RQA_ERR_INVALID_ARG, "offsets decrease at series %u", s);
-        const uint64_t n = offsets[s + 1] - offsets[s];
-        uint64_t nv, M;
-        if ((st = check_params(&p[s], n, &nv, &M))) {
-            char msg[512];
-            std::snprintf(msg, sizeof msg, "series %u: %s", s, g_err);
-            return fail(st, "%s", msg);
-        }
-        job.series.push_back({offsets[s], n, p[s]});
-        for (uint32_t r = 0; r < K; ++r)
-            if ((st = target_rank(rr[(size_t)s * K + r], M, &job.k[(size_t)s * K + r]))) return st;
-    }
+    if ((st = build_batch_job(job, S, concat, offsets, p, rr, K))) return st;
     if ((st = run_job(c, job))) return st;
     for (size_t i = 0; i < (size_t)S * K; ++i) {
         eps_out[i] = job.eps[i];
@@ -670,6 +893,94 @@ rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t
         if (count_out) count_out[i] = job.count[i];
     }
     for (uint32_t s = 0; s < S; ++s) det_mean_out[s] = job.det_mean[s];
+    return RQA_OK;
+}
+
+rqa_status rqa_autotune(rqa_ctx* c, const float* series, uint64_t n, const rqa_params* p, const double* rr, uint32_t K,
+                        uint32_t* segment_out, uint32_t* chunk_tiles_out)
+{
+    Job job;
+    rqa_status st = single_job_setup(c, job, series, n, p, rr, K);
+    if (st) return st;
+    return tune_job(c, job, segment_out, chunk_tiles_out);
+}
+
+rqa_status rqa_autotune_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,
+                              const rqa_params* p, const double* rr, uint32_t K, uint32_t* chunk_tiles_out)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    Job job;
+    if ((st = build_batch_job(job, S, concat, offsets, p, rr, K))) return st;
+    return tune_job(c, job, nullptr, chunk_tiles_out);
+}
+
+rqa_status rqa_sketch_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,
+                            const rqa_params* p, uint64_t seed, float* features_out, uint32_t* scale_out)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (S == 0 || !concat || !offsets || !p || !features_out) return fail(RQA_ERR_INVALID_ARG, "a required pointer is NULL");
+    Job job;
+    job.base = concat;
+    job.K = 1;
+    job.mode = MODE_SKETCH;
+    job.seed = seed;
+    for (uint32_t s = 0; s < S; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(RQA_ERR_INVALID_ARG, "offsets decrease at series %u", s);
+        uint64_t nv, M;
+        if ((st = check_params(&p[s], offsets[s + 1] - offsets[s], &nv, &M))) return st;
+        job.series.push_back({offsets[s], offsets[s + 1] - offsets[s], p[s]});
+    }
+    if ((st = run_job(c, job))) return st;
+    std::memcpy(features_out, job.features.data(), sizeof(float) * job.features.size());
+    if (scale_out) std::memcpy(scale_out, job.scale.data(), sizeof(uint32_t) * S);
+    return RQA_OK;
+}
+
+rqa_status rqa_tune_save(rqa_ctx* c, const char* path)
+{
+    if (!c || !path) return fail(RQA_ERR_INVALID_ARG, "context or path is NULL");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(RQA_ERR_INVALID_ARG, "cannot write %s", path);
+    std::fprintf(f, "{\"rqa_tune\": 1, \"entries\": [");
+    bool first = true;
+    for (const auto& kv : c->tune) {
+        std::fprintf(f, "%s\n  {\"nvlog2\": %d, \"variant\": %d, \"kcls\": %d, \"segment\": %u, \"chunk_tiles\": %u}",
+                     first ? "" : ",", kv.first.nvlog2, kv.first.variant, kv.first.kcls, kv.second.seg, kv.second.chunk);
+        first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    std::fclose(f);
+    return RQA_OK;
+}
+
+rqa_status rqa_tune_load(rqa_ctx* c, const char* path)
+{
+    if (!c || !path) return fail(RQA_ERR_INVALID_ARG, "context or path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(RQA_ERR_INVALID_ARG, "cannot read %s", path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    if (text.find("\"rqa_tune\": 1") == std::string::npos) return fail(RQA_ERR_INVALID_ARG, "%s is not a tuning table", path);
+    std::map<TuneKey, Shape> table;
+    size_t pos = 0;
+    while ((pos = text.find("{\"nvlog2\":", pos)) != std::string::npos) {
+        int nvlog2, variant, kcls;
+        unsigned seg, chunk;
+        if (std::sscanf(text.c_str() + pos,
+                        "{\"nvlog2\": %d, \"variant\": %d, \"kcls\": %d, \"segment\": %u, \"chunk_tiles\": %u}",
+                        &nvlog2, &variant, &kcls, &seg, &chunk) != 5)
+            return fail(RQA_ERR_INVALID_ARG, "malformed entry in %s", path);
+        if ((seg && (seg % TILE_W || seg > 65536)) || chunk == 0 || chunk > 4096)
+            return fail(RQA_ERR_INVALID_ARG, "out-of-range shape in %s", path);
+        table[TuneKey{nvlog2, variant, kcls}] = {seg, chunk};
+        ++pos;
+    }
+    c->tune = table;
     return RQA_OK;
 }
 
@@ -688,5 +999,198 @@ const char* rqa_status_string(rqa_status s)
 }
 
 const char* rqa_last_error(void) { return g_err; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ network
+
+namespace {
+
+rqa_status ensure_mlp(rqa_ctx* c)
+{
+    if (c->mlp) return RQA_OK;
+    if (hipMalloc(&c->mlp, sizeof(float) * 4 * MLP_PARAMS) != hipSuccess) {
+        c->mlp = nullptr;
+        (void)hipGetLastError();
+        return fail(RQA_ERR_NOMEM, "hipMalloc of the network failed");
+    }
+    if (hipMalloc(&c->mlp_partial, sizeof(float) * 4096) != hipSuccess) {
+        c->mlp_partial = nullptr;
+        (void)hipGetLastError();
+        return fail(RQA_ERR_NOMEM, "hipMalloc of the loss buffer failed");
+    }
+    HIP_TRY(launch_zero(c->stream, c->mlp, sizeof(float) * 4 * MLP_PARAMS));
+    return RQA_OK;
+}
+
+rqa_status ensure_acts(rqa_ctx* c, uint32_t B, MlpActs& a)
+{
+    if (B > c->mlp_cap) {
+        if (c->mlp_acts) (void)hipFree(c->mlp_acts);
+        c->mlp_acts = nullptr;
+        c->mlp_cap = 0;
+        const size_t per = 5 * MLP_H + 2 * MLP_OUT + MLP_H;  // Z1 A1 Z2 A2 dZ2 dZ1 + Y dY
+        if (hipMalloc(&c->mlp_acts, sizeof(float) * per * B) != hipSuccess) {
+            c->mlp_acts = nullptr;
+            (void)hipGetLastError();
+            return fail(RQA_ERR_NOMEM, "hipMalloc of network activations failed");
+        }
+        c->mlp_cap = B;
+    }
+    float* p = c->mlp_acts;
+    const size_t cap = c->mlp_cap;
+    a.Z1 = p; p += cap * MLP_H;
+    a.A1 = p; p += cap * MLP_H;
+    a.Z2 = p; p += cap * MLP_H;
+    a.A2 = p; p += cap * MLP_H;
+    a.dZ2 = p; p += cap * MLP_H;
+    a.dZ1 = p; p += cap * MLP_H;
+    a.Y = p; p += cap * MLP_OUT;
+    a.dY = p;
+    return RQA_OK;
+}
+
+rqa_status check_model(rqa_ctx* c, uint32_t B)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (!c->has_model) return fail(RQA_ERR_INVALID_ARG, "no network: call rqa_mlp_init or rqa_mlp_set_params");
+    if (B == 0 || B > 65536) return fail(RQA_ERR_INVALID_ARG, "batch %u outside 1..65536", B);
+    return RQA_OK;
+}
+
+// forward + backward into the gradient buffer; loss summed on the host
+rqa_status mlp_grad(rqa_ctx* c, const float* x, const float* t, uint32_t B, double* loss)
+{
+    MlpActs a;
+    rqa_status st = ensure_acts(c, B, a);
+    if (st) return st;
+    float* params = c->mlp;
+    float* grad = c->mlp + MLP_PARAMS;
+    HIP_TRY(mlp_forward(c->stream, params, x, (int)B, a, a.Y));
+    int np = 0;
+    HIP_TRY(mlp_backward(c->stream, params, x, t, (int)B, a, grad, c->mlp_partial, &np));
+    if (np > 4096) return fail(RQA_ERR_INVALID_ARG, "batch too large for the loss buffer");
+    float part[4096];
+    HIP_TRY(hipMemcpyAsync(part, c->mlp_partial, sizeof(float) * np, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (int i = 0; i < np; ++i) sum += part[i];
+    if (loss) *loss = sum;
+    return RQA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rqa_status rqa_mlp_init(rqa_ctx* c, uint64_t seed)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = ensure_mlp(c))) return st;
+    // He-uniform weights from the SplitMix64 stream `seed`, zero biases
+    std::vector<float> h(MLP_PARAMS, 0.f);
+    const MlpOffsets o;
+    uint64_t ctr = 0;
+    auto uni = [&]() {
+        uint64_t z = seed + (++ctr) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int off, int fan_in, int count) {
+        const double lim = std::sqrt(6.0 / fan_in);
+        for (int i = 0; i < count; ++i) h[off + i] = (float)((2.0 * uni() - 1.0) * lim);
+    };
+    fill(o.W1, MLP_IN, MLP_IN * MLP_H);
+    fill(o.W2, MLP_H, MLP_H * MLP_H);
+    fill(o.W3, MLP_H, MLP_H * MLP_OUT);
+    HIP_TRY(hipMemcpyAsync(c->mlp, h.data(), sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_zero(c->stream, c->mlp + MLP_PARAMS, sizeof(float) * 3 * MLP_PARAMS));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->adam_t = 0;
+    c->has_model = true;
+    return RQA_OK;
+}
+
+rqa_status rqa_mlp_set_params(rqa_ctx* c, const float* params, uint64_t count)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (!params || count != (uint64_t)MLP_PARAMS) return fail(RQA_ERR_INVALID_ARG, "need %d parameters", MLP_PARAMS);
+    for (uint64_t i = 0; i < count; ++i)
+        if (!std::isfinite(params[i])) return fail(RQA_ERR_NONFINITE, "parameter %llu is not finite", (unsigned long long)i);
+    if ((st = ensure_mlp(c))) return st;
+    HIP_TRY(hipMemcpyAsync(c->mlp, params, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_zero(c->stream, c->mlp + MLP_PARAMS, sizeof(float) * 3 * MLP_PARAMS));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->adam_t = 0;
+    c->has_model = true;
+    return RQA_OK;
+}
+
+rqa_status rqa_mlp_get_params(rqa_ctx* c, float* params, uint64_t count)
+{
+    rqa_status st = check_model(c, 1);
+    if (st) return st;
+    if (!params || count != (uint64_t)MLP_PARAMS) return fail(RQA_ERR_INVALID_ARG, "need %d parameters", MLP_PARAMS);
+    HIP_TRY(hipMemcpyAsync(params, c->mlp, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return RQA_OK;
+}
+
+rqa_status rqa_mlp_forward(rqa_ctx* c, const float* x_dev, uint32_t B, float* y_dev)
+{
+    rqa_status st = check_model(c, B);
+    if (st) return st;
+    if (!x_dev || !y_dev) return fail(RQA_ERR_INVALID_ARG, "a device pointer is NULL");
+    MlpActs a;
+    if ((st = ensure_acts(c, B, a))) return st;
+    HIP_TRY(mlp_forward(c->stream, c->mlp, x_dev, (int)B, a, y_dev));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return RQA_OK;
+}
+
+rqa_status rqa_mlp_gradients(rqa_ctx* c, const float* x_dev, const float* t_dev, uint32_t B, float* grad_out,
+                             double* loss_out)
+{
+    rqa_status st = check_model(c, B);
+    if (st) return st;
+    if (!x_dev || !t_dev || !grad_out) return fail(RQA_ERR_INVALID_ARG, "a pointer is NULL");
+    if ((st = mlp_grad(c, x_dev, t_dev, B, loss_out))) return st;
+    HIP_TRY(hipMemcpyAsync(grad_out, c->mlp + MLP_PARAMS, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return RQA_OK;
+}
+
+rqa_status rqa_mlp_train_step(rqa_ctx* c, const float* x_dev, const float* t_dev, uint32_t B, float lr,
+                              double* loss_out)
+{
+    rqa_status st = check_model(c, B);
+    if (st) return st;
+    if (!x_dev || !t_dev) return fail(RQA_ERR_INVALID_ARG, "a device pointer is NULL");
+    if (!(lr > 0.f) || !std::isfinite(lr)) return fail(RQA_ERR_INVALID_ARG, "learning rate must be positive");
+    if ((st = mlp_grad(c, x_dev, t_dev, B, loss_out))) return st;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    c->adam_t += 1;
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)c->adam_t));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)c->adam_t));
+    HIP_TRY(mlp_adam(c->stream, c->mlp, c->mlp + MLP_PARAMS, c->mlp + 2 * MLP_PARAMS, c->mlp + 3 * MLP_PARAMS, lr, b1,
+                     b2, eps, c1, c2));
+    return RQA_OK;
+}
+
+rqa_status rqa_mlp_set_bracket(rqa_ctx* c, const float* delta, uint32_t n)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (!delta || n != (uint32_t)MLP_OUT) return fail(RQA_ERR_INVALID_ARG, "need %d half-widths", MLP_OUT);
+    for (uint32_t i = 0; i < n; ++i)
+        if (!(delta[i] >= 0.f) || !std::isfinite(delta[i])) return fail(RQA_ERR_INVALID_ARG, "half-width %u invalid", i);
+    std::memcpy(c->bracket_delta, delta, sizeof(float) * MLP_OUT);
+    return RQA_OK;
+}
 
 }  // extern "C"

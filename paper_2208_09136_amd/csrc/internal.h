@@ -15,15 +15,16 @@ constexpr int TILE_W = 64;
 
 // Radix split of the 31 significant bits of a key (the sign bit is always 0):
 // pass 1 histograms the top SEL_B1 bits for every pair; pass 2 the next SEL_B2
-// bits of keys whose pass-1 prefix holds a target; pass 3 the last SEL_B3 bits.
+// bits of keys whose pass-1 prefix holds a target; pass 3 the last SEL_B3 bits
+// of keys whose 21-bit prefix holds a target.
 constexpr int SEL_B1 = 12;
-constexpr int SEL_B2 = 10;
-constexpr int SEL_B3 = 9;
+constexpr int SEL_B2 = 9;
+constexpr int SEL_B3 = 10;
 constexpr int SEL_SH1 = 31 - SEL_B1;           // 19
-constexpr int SEL_SH2 = SEL_SH1 - SEL_B2;      // 9
+constexpr int SEL_SH2 = SEL_SH1 - SEL_B2;      // 10
 constexpr uint32_t SEL_N1 = 1u << SEL_B1;      // 4096
-constexpr uint32_t SEL_N2 = 1u << SEL_B2;      // 1024
-constexpr uint32_t SEL_N3 = 1u << SEL_B3;      // 512
+constexpr uint32_t SEL_N2 = 1u << SEL_B2;      // 512
+constexpr uint32_t SEL_N3 = 1u << SEL_B3;      // 1024
 constexpr uint8_t NO_SLOT = 0xFF;
 
 // Threshold-rank lookup table of the sweep: RHO_TABLE buckets of the key's
@@ -50,7 +51,15 @@ struct SeriesDesc {
     uint32_t chunk_begin;  // first global chunk index of this series
     uint32_t nchunks;      // chunks of this series
     uint32_t variant;      // kernel variant (norm/m/lmin class), host bookkeeping
+    uint64_t seed;         // sketch sampling stream
+    float f_logn, f_m;     // sketch features log2(n)/16 and m/4
 };
+
+// Distance sketch: SKETCH_P sampled pairs, SKETCH_BINS bins of a quarter
+// binade around the sample median, plus two shape features.
+constexpr int SKETCH_P = 4096;
+constexpr int SKETCH_BINS = 64;
+constexpr int SKETCH_FEATURES = SKETCH_BINS + 2;
 
 // Per-series working state in device memory.
 struct SeriesWork {
@@ -67,10 +76,12 @@ struct SeriesWork {
     uint32_t dmap[RQA_MAX_K];     // caller index -> distinct index
     uint32_t Kp;                  // distinct thresholds
     uint32_t shift, emin, emax;   // rank-table geometry
+    uint32_t multi;               // some bucket of the rank table holds several thresholds
     uint64_t hrho[RQA_MAX_K + 1]; // cells with rank rho (rho < Kp)
     uint64_t hlam[RQA_MAX_K + 1]; // cells with line rank lambda (lambda < Kp)
     uint32_t nonfinite;           // set when a sample is NaN or infinite
     uint32_t status;              // device-side error bits (0 = fine)
+    uint32_t scale;               // sketch: bit pattern of the sample median
 };
 
 // Device buffers of one call (host-side handle).
@@ -101,11 +112,19 @@ hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass);
 hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b);
 hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, uint32_t grid,
                         uint32_t block, uint32_t ticket);
+// Sketch of every series: features [S][SKETCH_FEATURES], sorted sample bits
+// [S][SKETCH_P] (may be NULL), scale into SeriesWork.
+hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint32_t* sample_sorted);
 
-// Kernel variants: norm x embedding class x line-length class.
-enum MClass { MC_ANY = 0, MC_1 = 1, MC_3 = 3 };
-int variant_of(uint32_t norm, uint32_t m, uint32_t lmin);
-int select_variant_of(uint32_t norm, uint32_t m);
+// Kernel variants.  Embedding class: 0 any (m, tau) at run time, 1 m = 1,
+// 2 m = 3 with tau = 3, 3 m = 3 with tau = 5.  Line class: 0 any lmin,
+// 1 lmin = 1, 2 lmin = 2.  select variant = norm * 4 + embedding class;
+// sweep variant = select variant * 3 + line class.
+constexpr int NUM_MCLASS = 4;
+constexpr int NUM_SELECT_VARIANTS = 2 * NUM_MCLASS;
+constexpr int NUM_SWEEP_VARIANTS = NUM_SELECT_VARIANTS * 3;
+int select_variant_of(uint32_t norm, uint32_t m, uint32_t tau);
+int variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin);
 
 // Dynamic LDS bytes of each kernel for a K and group size.
 size_t select_lds_bytes(int pass, uint32_t K, uint32_t group_slots);

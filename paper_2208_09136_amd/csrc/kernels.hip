@@ -1,9 +1,9 @@
 // kernels.hip -- gfx950 kernels of the averaged-RQA hot path.
 //
-// Work decomposition (every kernel): the pairs (i, j = i + d) of one series
-// form the upper triangle of diagonals d = w .. nv-1.  A tile is one band of
-// 64 consecutive diagonals times one segment of T steps along them; lane L of
-// the wavefront that owns the tile walks diagonal d0 + L.  Tiles are
+// Work decomposition (every counting kernel): the pairs (i, j = i + d) of one
+// series form the upper triangle of diagonals d = w .. nv-1.  A tile is one
+// band of 64 consecutive diagonals times one segment of T steps along them;
+// lane L of the wavefront that owns the tile walks diagonal d0 + L.  Tiles are
 // enumerated segment-major (all bands of segment 0, then of segment 1, ...),
 // grouped into chunks of consecutive tiles of one series, and chunks are
 // handed to persistent workgroups through an atomic ticket.  The recurrence
@@ -14,6 +14,13 @@
 // arithmetic is binary32 with round-to-nearest-even and no contraction, so the
 // keys (and every count derived from them) are bit-identical to a plain CPU
 // evaluation.
+//
+// Along a diagonal d the embedding component k of the pair (x, x + d) is the
+// difference e(s) = y[s] - y[s + d] at s = x + (m-1-k) tau, so each lane keeps
+// |e| or e^2 of the last (m-1) tau steps in registers and needs one new
+// difference per step (the "walker").  Tiles whose every lane stays inside its
+// diagonal take that path without per-lane bounds checks; border tiles and
+// run-time (m, tau) take a plain per-cell path.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,28 +31,54 @@
 
 namespace rqa {
 
+typedef const float __attribute__((address_space(1))) gf32;  // global
+typedef const float __attribute__((address_space(4))) cf32;  // constant: scalar loads for uniform indices
+
 // ------------------------------------------------------------------ helpers
 
-__device__ __forceinline__ void tile_coords(const SeriesDesc& sd, uint32_t tile, uint32_t& band,
-                                            uint32_t& seg)
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Per-series scalars of the tile loops (wave-uniform).
+struct SeriesScalars {
+    const float* y;
+    int n, nv, m, tau, w, T, q, B, Smax, ntiles;
+};
+
+__device__ __forceinline__ SeriesScalars load_scalars(const SeriesDesc& sd)
+{
+    SeriesScalars s;
+    s.y = sd.y;
+    s.n = (int)sd.n;
+    s.nv = (int)sd.nv;
+    s.m = (int)sd.m;
+    s.tau = (int)sd.tau;
+    s.w = (int)sd.w;
+    s.T = (int)sd.T;
+    s.q = (int)sd.q;
+    s.B = (int)sd.B;
+    s.Smax = (int)sd.Smax;
+    s.ntiles = (int)sd.ntiles;
+    return s;
+}
+
+__device__ __forceinline__ void tile_coords(const SeriesScalars& sd, uint32_t tile, uint32_t& band, uint32_t& seg)
 {
     // Segment s holds B - s*q bands, so tiles before segment s number
     // P(s) = s*B - q*s*(s-1)/2.  Invert with the quadratic formula and fix up.
-    const uint64_t B = sd.B, q = sd.q;
+    const uint64_t B = (uint64_t)sd.B, q = (uint64_t)sd.q, Smax = (uint64_t)sd.Smax;
     auto P = [&](uint64_t s) -> uint64_t { return s * B - q * ((s * (s - 1)) / 2); };
     const double Bq = (double)B + 0.5 * (double)q;
     const double disc = Bq * Bq - 2.0 * (double)q * (double)tile;
     const double est = (Bq - sqrt(disc > 0.0 ? disc : 0.0)) / (double)q;
     uint64_t s = est > 0.0 ? (uint64_t)est : 0;
-    if (s > sd.Smax - 1) s = sd.Smax - 1;
+    if (s > Smax - 1) s = Smax - 1;
     while (s > 0 && P(s) > tile) --s;
-    while (s + 1 < sd.Smax && P(s + 1) <= tile) ++s;
+    while (s + 1 < Smax && P(s + 1) <= tile) ++s;
     seg = (uint32_t)s;
     band = (uint32_t)(tile - P(s));
 }
 
-__device__ __forceinline__ uint32_t find_series(const SeriesDesc* __restrict__ sds, uint32_t S,
-                                                uint32_t chunk)
+__device__ __forceinline__ uint32_t find_series(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t chunk)
 {
     uint32_t lo = 0, hi = S;  // largest s with chunk_begin <= chunk
     while (hi - lo > 1) {
@@ -55,28 +88,45 @@ __device__ __forceinline__ uint32_t find_series(const SeriesDesc* __restrict__ s
     return lo;
 }
 
+template <int NORM>
+__device__ __forceinline__ float part_of(float e)
+{
+    if constexpr (NORM == RQA_NORM_MAX) return fabsf(e);
+    else return e * e;
+}
+
+template <int NORM>
+__device__ __forceinline__ float fold(float acc, float v)
+{
+    if constexpr (NORM == RQA_NORM_MAX) return fmaxf(acc, v);
+    else return acc + v;
+}
+
 // Distance key of vectors i and j: component k is y[i + (m-1-k) tau].
-template <int NORM, int MC>
+// MC > 0: m = MC and tau = TC (TC > 0) or run-time tau (TC = 0).
+template <int NORM, int MC, int TC>
 __device__ __forceinline__ float pair_key(const float* __restrict__ y, int i, int j, int m, int tau)
 {
-    float acc = 0.0f;
+    const gf32* g = (const gf32*)y;
     if constexpr (MC > 0) {
+        const int tt = TC > 0 ? TC : tau;
+        float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < MC; ++k) {
-            const int off = (MC - 1 - k) * tau;
-            const float d = y[i + off] - y[j + off];
-            if constexpr (NORM == RQA_NORM_MAX) acc = fmaxf(acc, fabsf(d));
-            else acc = (k == 0) ? d * d : acc + d * d;
+            const int off = (MC - 1 - k) * tt;
+            const float p = part_of<NORM>(g[i + off] - g[j + off]);
+            acc = (k == 0) ? p : fold<NORM>(acc, p);
         }
+        return acc;
     } else {
+        float acc = 0.0f;
         int off = (m - 1) * tau;
         for (int k = 0; k < m; ++k, off -= tau) {
-            const float d = y[i + off] - y[j + off];
-            if constexpr (NORM == RQA_NORM_MAX) acc = fmaxf(acc, fabsf(d));
-            else acc = (k == 0) ? d * d : acc + d * d;
+            const float p = part_of<NORM>(g[i + off] - g[j + off]);
+            acc = (k == 0) ? p : fold<NORM>(acc, p);
         }
+        return acc;
     }
-    return acc;
 }
 
 // Geometry of one tile for the calling lane.
@@ -84,23 +134,112 @@ struct TileGeo {
     int d;     // this lane's diagonal
     int d0;    // the band's first diagonal (always < nv)
     int len;   // cells on this lane's diagonal (0 past the last diagonal)
+    int len0;  // cells on the band's first (longest) diagonal
     int t0;    // first step of the segment
     int t1;    // one past the last step of the segment on the band's longest diagonal
 };
 
-__device__ __forceinline__ TileGeo tile_geo(const SeriesDesc& sd, uint32_t tile, int lane)
+__device__ __forceinline__ TileGeo tile_geo(const SeriesScalars& sd, uint32_t tile, int lane)
 {
     uint32_t band, seg;
     tile_coords(sd, tile, band, seg);
     TileGeo g;
-    g.d0 = (int)(sd.w + band * TILE_W);
+    g.d0 = (int)uniform((uint32_t)sd.w + band * TILE_W);
     g.d = g.d0 + lane;
-    g.len = g.d < (int)sd.nv ? (int)sd.nv - g.d : 0;
-    g.t0 = (int)(seg * sd.T);
-    const int len0 = (int)sd.nv - g.d0;
-    g.t1 = min(g.t0 + (int)sd.T, len0);
+    g.len = g.d < sd.nv ? sd.nv - g.d : 0;
+    g.len0 = sd.nv - g.d0;
+    g.t0 = (int)uniform(seg * (uint32_t)sd.T);
+    g.t1 = min(g.t0 + sd.T, g.len0);
     return g;
 }
+
+// Sequential key generator of one lane along its diagonal for compile-time
+// (M, TAU).  part_of(e(s)) of W = (M-1) TAU steps ahead of the next cell is
+// kept in a register ring of two halves of HU entries (HU a multiple of W, at
+// least 8): each half-block writes HU new parts into one half while the last W
+// parts of the other half serve as history, so the ring never moves.  Row
+// samples y[s] are wave-uniform (scalar loads); column samples y[s + d] are
+// one coalesced load per step at an immediate offset from the lane pointer.
+template <int NORM, int M, int TAU>
+struct Walker {
+    static constexpr int W = (M - 1) * TAU;
+    static constexpr int HU = W == 0 ? 8 : ((8 + W - 1) / W) * W;
+    float ring[2 * HU];
+    const gf32* cp;  // y + d + x (this lane's column samples)
+    const cf32* rp;  // y + x (row samples, uniform)
+
+    __device__ __forceinline__ void start(const float* y, int d, int x0)
+    {
+        cp = (const gf32*)y + (uint32_t)(d + x0);
+        rp = (const cf32*)y + (uint32_t)x0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) ring[2 * HU - W + i] = part_of<NORM>(rp[i] - cp[i]);
+    }
+    // part at virtual position v of the half-block that writes half H: v < W is
+    // history (tail of the other half), v >= W the new part of step v - W.
+    template <int H>
+    __device__ __forceinline__ float at(int v) const
+    {
+        return v >= W ? ring[H * HU + (v >= W ? v - W : 0)] : ring[(1 - H) * HU + HU - W + (v < W ? v : 0)];
+    }
+    // keys (binary32 bit patterns) of the next HU cells
+    template <int H>
+    __device__ __forceinline__ void half(uint32_t (&out)[HU])
+    {
+#pragma unroll
+        for (int u = 0; u < HU; ++u) ring[H * HU + u] = part_of<NORM>(rp[W + u] - cp[W + u]);
+#pragma unroll
+        for (int u = 0; u < HU; ++u) {
+            float acc = at<H>(u + W);  // component 0: the newest sample
+#pragma unroll
+            for (int k = 1; k < M; ++k) acc = fold<NORM>(acc, at<H>(u + W - k * TAU));
+            out[u] = __float_as_uint(acc);
+        }
+        cp += HU;
+        rp += HU;
+    }
+};
+
+// Margin (cells) an interior tile keeps beyond its last cell: the walker may
+// compute up to HU - 1 cells past the end of the requested range.
+constexpr int WALK_SLACK = 32;
+
+// Calls fb(keys, valid) for the cells x = x0 .. x0+count-1 of the lane's
+// diagonal, in order, one half-block of HU keys at a time; only the first
+// `valid` keys of a call are cells of the range (valid = HU except at the
+// end).  Every lane must own cells up to x0 + count - 1 + WALK_SLACK.
+template <int NORM, int M, int TAU, class FB>
+__device__ __forceinline__ void walk(const float* y, int d, int x0, int count, FB&& fb)
+{
+    using WK = Walker<NORM, M, TAU>;
+    constexpr int HU = WK::HU;
+    static_assert(HU < WALK_SLACK, "walker slack");
+    WK wk;
+    wk.start(y, d, x0);
+    int rem = count;
+    while (rem >= 2 * HU) {
+        uint32_t k[HU];
+        wk.template half<0>(k);
+        fb(k, HU);
+        wk.template half<1>(k);
+        fb(k, HU);
+        rem -= 2 * HU;
+    }
+    if (rem > 0) {
+        uint32_t k[HU];
+        wk.template half<0>(k);
+        fb(k, min(rem, HU));
+        rem -= HU;
+        if (rem > 0) {
+            wk.template half<1>(k);
+            fb(k, rem);
+        }
+    }
+}
+
+// Number of keys per call of a walk callback.
+template <int NORM, int M, int TAU>
+constexpr int walk_block() { return Walker<NORM, M, TAU>::HU; }
 
 // ------------------------------------------------------------------ zero / checks
 
@@ -138,34 +277,35 @@ hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn)
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ selection
+// ------------------------------------------------------------------ work loop
 
-// Persistent work loop shared by the counting kernels: grab chunks from the
-// ticket, switch per-series LDS state when the series changes, process the
+// Persistent work loop shared by the counting kernels (s_chunk_slot: one LDS
+// word shared by the workgroup): grab chunks from the ticket, switch per-series LDS state when the series changes, process the
 // chunk's tiles one per wavefront, flush accumulated counts when the series
 // changes, when 32-bit LDS counters could overflow, and at the end.
 template <class Body>
-__device__ __forceinline__ void chunk_loop(const SeriesDesc* __restrict__ sds, uint32_t S,
-                                           uint32_t nchunks, uint32_t chunk_tiles,
-                                           uint32_t* __restrict__ ticket, Body& body)
+__device__ __forceinline__ void chunk_loop(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks,
+                                           uint32_t chunk_tiles, uint32_t* __restrict__ ticket, Body& body,
+                                           uint32_t* s_chunk_slot)
 {
-    __shared__ uint32_t s_chunk;
+    uint32_t& s_chunk = *s_chunk_slot;
     uint32_t cur = 0xFFFFFFFFu;
     uint64_t acc = 0;
     const int wave = threadIdx.x / TILE_W;
     const int nwaves = blockDim.x / TILE_W;
     const int lane = threadIdx.x % TILE_W;
+    SeriesScalars ss{};
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_chunk = atomicAdd(ticket, 1u);
         __syncthreads();
-        const uint32_t c = s_chunk;
+        const uint32_t c = uniform(s_chunk);
         if (c >= nchunks) {
             // queue drained (possibly before this workgroup drew its first chunk)
             if (cur != 0xFFFFFFFFu) body.flush(cur);
             break;
         }
-        const uint32_t s = find_series(sds, S, c);
+        const uint32_t s = uniform(find_series(sds, S, c));
         const SeriesDesc& sd = sds[s];
         const uint64_t chunk_cells = (uint64_t)chunk_tiles * TILE_W * sd.T;
         if (s != cur || acc + chunk_cells > 0xFFFFFFFFull) {
@@ -175,19 +315,77 @@ __device__ __forceinline__ void chunk_loop(const SeriesDesc* __restrict__ sds, u
             __syncthreads();
             cur = s;
             acc = 0;
+            ss = load_scalars(sd);
         }
         if (body.active) {
             const uint32_t lc = c - sd.chunk_begin;
             const uint32_t tb = lc * chunk_tiles;
-            const uint32_t te = min(tb + chunk_tiles, sd.ntiles);
-            for (uint32_t tile = tb + wave; tile < te; tile += nwaves) body.tile(sd, tile, lane);
+            const uint32_t te = min(tb + chunk_tiles, (uint32_t)ss.ntiles);
+            for (uint32_t tile = tb + wave; tile < te; tile += nwaves) body.tile(ss, uniform(tile), lane);
         }
         acc += chunk_cells;
     }
 }
 
+// Adds 1 to slot base[idx] for every active lane, one atomic per distinct idx
+// among the active lanes.
+__device__ __forceinline__ void wave_add(unsigned long long* base, uint32_t idx, bool active)
+{
+    uint64_t mask = __ballot(active);
+    while (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        const uint32_t li = __builtin_amdgcn_readlane(idx, leader);
+        const uint64_t same = __ballot(active && idx == li);
+        if ((int)__lane_id() == leader) atomicAdd(base + li, (unsigned long long)__popcll(same));
+        active = active && idx != li;
+        mask &= ~same;
+    }
+}
+
+// ------------------------------------------------------------------ selection
+
+// Shared tile driver of the selection passes.  For every cell of the lane's
+// diagonal in the tile: look = body.look(key) (LDS table reads, issued for a
+// whole block of keys first), then body.count(key, look).
+template <int NORM, int MC, int TC, class Body>
+__device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t tile_id, int lane, Body& body)
+{
+    const TileGeo g = tile_geo(sd, tile_id, lane);
+    constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
+    if constexpr (kFast) {
+        constexpr int TW = MC == 1 ? 1 : TC;
+        constexpr int HU = walk_block<NORM, MC, TW>();
+        if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
+            // interior: every lane's diagonal covers [t0, t1 + WALK_SLACK]
+            walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                uint32_t lk[HU];
+#pragma unroll
+                for (int u = 0; u < HU; ++u) lk[u] = body.look(k[u]);
+#pragma unroll
+                for (int u = 0; u < HU; ++u)
+                    if (u < valid) body.count(k[u], lk[u]);
+            });
+            return;
+        }
+    }
+    for (int x = g.t0; x < g.t1; ++x) {
+        if (x < g.len) {
+            const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau));
+            body.count(u, body.look(u));
+        }
+    }
+}
+
+// Bytes of a selection pass's LDS tables and bins; the work-queue word follows.
+__host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G)
+{
+    if (pass == 1) return SEL_N1 * 4;
+    if (pass == 2) return SEL_N1 + (size_t)G * SEL_N2 * 4;
+    return SEL_N1 + (size_t)K * SEL_N2;
+}
+
 // Pass 1: histogram of the top SEL_B1 bits of every key.
-template <int NORM, int MC>
+template <int NORM, int MC, int TC>
 struct SelPass1 {
     uint32_t* bins;   // LDS [SEL_N1]
     uint64_t* h1;     // global [S][SEL_N1]
@@ -203,23 +401,20 @@ struct SelPass1 {
             if (v) atomicAdd((unsigned long long*)&h1[(size_t)s * SEL_N1 + i], (unsigned long long)v);
         }
     }
-    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
+    __device__ __forceinline__ void count(uint32_t u, uint32_t) const
     {
-        const TileGeo g = tile_geo(sd, tile_id, lane);
-        const float* __restrict__ y = sd.y;
-        const int m = sd.m, tau = sd.tau;
-        for (int x = g.t0; x < g.t1; ++x) {
-            if (x < g.len) {
-                const uint32_t u = __float_as_uint(pair_key<NORM, MC>(y, x, x + g.d, m, tau)) & 0x7FFFFFFFu;
-                atomicAdd(&bins[u >> SEL_SH1], 1u);
-            }
-        }
+        atomicAdd(&bins[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)], 1u);
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-// Pass 2: for keys whose pass-1 bucket holds a target (slot in [lo, lo+G)),
+// Pass 2: for keys whose pass-1 bucket holds a target (slot in [lo, hi)),
 // histogram the next SEL_B2 bits per slot.
-template <int NORM, int MC>
+template <int NORM, int MC, int TC>
 struct SelPass2 {
     uint8_t* sT1;     // LDS [SEL_N1]
     uint32_t* bins;   // LDS [G][SEL_N2]
@@ -246,75 +441,59 @@ struct SelPass2 {
             if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
         }
     }
-    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    // slot of the key's pass-1 bucket relative to this group (>= span: none)
+    __device__ __forceinline__ uint32_t look(uint32_t u) const
     {
-        const TileGeo g = tile_geo(sd, tile_id, lane);
-        const float* __restrict__ y = sd.y;
-        const int m = sd.m, tau = sd.tau;
-        for (int x = g.t0; x < g.t1; ++x) {
-            if (x < g.len) {
-                const uint32_t u = __float_as_uint(pair_key<NORM, MC>(y, x, x + g.d, m, tau)) & 0x7FFFFFFFu;
-                const uint32_t sl = sT1[u >> SEL_SH1];
-                if (sl >= lo && sl < hi)
-                    atomicAdd(&bins[(sl - lo) * SEL_N2 + ((u >> SEL_SH2) & (SEL_N2 - 1))], 1u);
-            }
-        }
+        return (uint32_t)sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)] - lo;
+    }
+    __device__ __forceinline__ void count(uint32_t u, uint32_t rel) const
+    {
+        if (rel < hi - lo) atomicAdd(&bins[rel * SEL_N2 + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)], 1u);
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-// Pass 3: for keys whose 22-bit prefix holds a target (pass-3 slot in
-// [lo, lo+G)), histogram the last SEL_B3 bits per slot.
-template <int NORM, int MC>
+// Pass 3: for keys whose 21-bit prefix holds a target, count the last SEL_B3
+// bits per pass-3 slot directly in global memory (few keys qualify).
+template <int NORM, int MC, int TC>
 struct SelPass3 {
     uint8_t* sT1;     // LDS [SEL_N1]
     uint8_t* sT2;     // LDS [K][SEL_N2]
-    uint32_t* bins;   // LDS [G][SEL_N3]
     const uint8_t* T1;
     const uint8_t* T2;
     const SeriesWork* works;
     uint64_t* h3;     // global [S][K][SEL_N3]
-    uint32_t K, G, lo, hi;
+    uint32_t K;
+    unsigned long long* dst;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
-        const uint32_t ns = works[s].nslots3;
         const uint32_t n2 = works[s].nslots2;
-        hi = min(lo + G, ns);
-        active = lo < ns;
         for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
-        for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x)
-            sT2[i] = T2[(size_t)s * K * SEL_N2 + i];
-        for (uint32_t i = threadIdx.x; i < G * SEL_N3; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) sT2[i] = T2[(size_t)s * K * SEL_N2 + i];
+        dst = (unsigned long long*)(h3 + (size_t)s * K * SEL_N3);
     }
-    __device__ void flush(uint32_t s)
+    __device__ void flush(uint32_t) {}
+    // pass-3 slot of the key's 21-bit prefix (NO_SLOT: none)
+    __device__ __forceinline__ uint32_t look(uint32_t u) const
     {
-        if (!active) return;
-        const uint32_t n = (hi - lo) * SEL_N3;
-        uint64_t* dst = h3 + ((size_t)s * K + lo) * SEL_N3;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t v = bins[i];
-            if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
-        }
+        const uint32_t s2 = sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
+        return s2 != NO_SLOT ? (uint32_t)sT2[s2 * SEL_N2 + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)] : NO_SLOT;
     }
-    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    __device__ __forceinline__ void count(uint32_t u, uint32_t s3) const
     {
-        const TileGeo g = tile_geo(sd, tile_id, lane);
-        const float* __restrict__ y = sd.y;
-        const int m = sd.m, tau = sd.tau;
-        for (int x = g.t0; x < g.t1; ++x) {
-            if (x < g.len) {
-                const uint32_t u = __float_as_uint(pair_key<NORM, MC>(y, x, x + g.d, m, tau)) & 0x7FFFFFFFu;
-                const uint32_t s2 = sT1[u >> SEL_SH1];
-                if (s2 != NO_SLOT) {
-                    const uint32_t s3 = sT2[s2 * SEL_N2 + ((u >> SEL_SH2) & (SEL_N2 - 1))];
-                    if (s3 >= lo && s3 < hi) atomicAdd(&bins[(s3 - lo) * SEL_N3 + (u & (SEL_N3 - 1))], 1u);
-                }
-            }
-        }
+        wave_add(dst, s3 * SEL_N3 + (u & (SEL_N3 - 1)), s3 != NO_SLOT);
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-template <int PASS, int NORM, int MC>
+template <int PASS, int NORM, int MC, int TC>
 __global__ void __launch_bounds__(1024)
 k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
          uint32_t* __restrict__ tickets, SeriesWork* __restrict__ works, const uint8_t* __restrict__ T1,
@@ -322,11 +501,12 @@ k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint3
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* ticket = tickets + blockIdx.y;
+    uint32_t* slot = (uint32_t*)(smem + select_lds_bytes_dev(PASS, K, G));
     if constexpr (PASS == 1) {
-        SelPass1<NORM, MC> body{(uint32_t*)smem, hist};
-        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+        SelPass1<NORM, MC, TC> body{(uint32_t*)smem, hist};
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else if constexpr (PASS == 2) {
-        SelPass2<NORM, MC> body;
+        SelPass2<NORM, MC, TC> body;
         body.sT1 = (uint8_t*)smem;
         body.bins = (uint32_t*)(smem + SEL_N1);
         body.T1 = T1;
@@ -336,51 +516,58 @@ k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint3
         body.G = G;
         body.lo = blockIdx.y * G;
         body.hi = body.lo;
-        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else {
-        SelPass3<NORM, MC> body;
+        SelPass3<NORM, MC, TC> body;
         body.sT1 = (uint8_t*)smem;
         body.sT2 = (uint8_t*)(smem + SEL_N1);
-        body.bins = (uint32_t*)(smem + SEL_N1 + (size_t)K * SEL_N2);
         body.T1 = T1;
         body.T2 = T2;
         body.works = works;
         body.h3 = hist;
         body.K = K;
-        body.G = G;
-        body.lo = blockIdx.y * G;
-        body.hi = body.lo;
-        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+        body.dst = nullptr;
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     }
 }
 
-size_t select_lds_bytes(int pass, uint32_t K, uint32_t G)
+size_t select_lds_bytes(int pass, uint32_t K, uint32_t G) { return select_lds_bytes_dev(pass, K, G) + 16; }
+
+static int mclass_of(uint32_t m, uint32_t tau)
 {
-    if (pass == 1) return SEL_N1 * 4;
-    if (pass == 2) return SEL_N1 + (size_t)G * SEL_N2 * 4;
-    return SEL_N1 + (size_t)K * SEL_N2 + (size_t)G * SEL_N3 * 4;
+    if (m == 1) return 1;
+    if (m == 3 && tau == 3) return 2;
+    if (m == 3 && tau == 5) return 3;
+    return 0;
 }
 
-int select_variant_of(uint32_t norm, uint32_t m)
+int select_variant_of(uint32_t norm, uint32_t m, uint32_t tau) { return (int)norm * NUM_MCLASS + mclass_of(m, tau); }
+
+int variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
 {
-    const int mc = (m == 1) ? 1 : (m == 3) ? 2 : 0;
-    return (int)norm * 3 + mc;
+    const int lc = (lmin == 1) ? 1 : (lmin == 2) ? 2 : 0;
+    return select_variant_of(norm, m, tau) * 3 + lc;
 }
 
-using SelFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*,
-                       const uint8_t*, const uint8_t*, uint64_t*, uint32_t, uint32_t);
+using SelFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint8_t*,
+                       const uint8_t*, uint64_t*, uint32_t, uint32_t);
+
+template <int PASS, int NORM>
+static SelFn select_fn_n(int mclass)
+{
+    switch (mclass) {
+    case 1: return k_select<PASS, NORM, 1, 0>;
+    case 2: return k_select<PASS, NORM, 3, 3>;
+    case 3: return k_select<PASS, NORM, 3, 5>;
+    default: return k_select<PASS, NORM, 0, 0>;
+    }
+}
 
 template <int PASS>
 static SelFn select_fn(int variant)
 {
-    switch (variant) {
-    case 0: return k_select<PASS, RQA_NORM_MAX, MC_ANY>;
-    case 1: return k_select<PASS, RQA_NORM_MAX, MC_1>;
-    case 2: return k_select<PASS, RQA_NORM_MAX, MC_3>;
-    case 3: return k_select<PASS, RQA_NORM_EUCLIDEAN, MC_ANY>;
-    case 4: return k_select<PASS, RQA_NORM_EUCLIDEAN, MC_1>;
-    default: return k_select<PASS, RQA_NORM_EUCLIDEAN, MC_3>;
-    }
+    const int norm = variant / NUM_MCLASS, mc = variant % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? select_fn_n<PASS, RQA_NORM_MAX>(mc) : select_fn_n<PASS, RQA_NORM_EUCLIDEAN>(mc);
 }
 
 static SelFn select_fn_pass(int pass, int variant)
@@ -536,11 +723,9 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
     if (threadIdx.x == 0) nuniq = sort_unique(uniq, K);
     __syncthreads();
     const uint32_t nu = nuniq;
-    __syncthreads();
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
         const uint32_t u = index_of(uniq, nu, w.prefix[r]);
-        const uint32_t s2 = w.slot[r];
-        t2[s2 * SEL_N2 + (w.prefix[r] & (SEL_N2 - 1))] = (uint8_t)u;
+        t2[w.slot[r] * SEL_N2 + (w.prefix[r] & (SEL_N2 - 1))] = (uint8_t)u;
     }
     __syncthreads();
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
@@ -587,31 +772,26 @@ hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass)
 struct RhoCtx {
     const uint2* table;     // LDS [RHO_TABLE]: x = first threshold in bucket (or ~0), y = rank base
     const uint32_t* es;     // LDS [Kp] distinct thresholds
-    uint32_t emin, emax, shift, Kp;
+    float emin, emax;       // smallest and largest threshold
+    uint32_t shift, Kp;
 };
 
+// MULTI: some bucket holds more than one threshold (rare; flagged per series).
+template <bool MULTI>
 __device__ __forceinline__ uint32_t rho_of(uint32_t u, const RhoCtx& c)
 {
-    const uint32_t cl = min(max(u, c.emin), c.emax);
-    const uint2 e = c.table[(cl >> c.shift) & (RHO_TABLE - 1)];
+    // keys and thresholds are non-negative floats: they order like their bits
+    const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
+    const uint2 e = c.table[__builtin_amdgcn_ubfe(cl, c.shift, RHO_BITS)];
     uint32_t r = e.y + (u > e.x ? 1u : 0u);
-    if (e.y >= RHO_MULTI) {
-        const uint32_t base = e.y & 0xFFFFu, cnt = e.y >> 16;
-        r = base;
-        for (uint32_t i = 0; i < cnt; ++i) r += (u > c.es[base + i]) ? 1u : 0u;
+    if constexpr (MULTI) {
+        if (e.y >= RHO_MULTI) {
+            const uint32_t base = e.y & 0xFFFFu, cnt = e.y >> 16;
+            r = base;
+            for (uint32_t i = 0; i < cnt; ++i) r += (u > c.es[base + i]) ? 1u : 0u;
+        }
     }
     return r;
-}
-
-template <int NORM, int MC>
-__device__ __forceinline__ uint32_t rho_at(const SeriesDesc& sd, const TileGeo& g, int x, const RhoCtx& rc)
-{
-    const bool ok = (x >= 0) && (x < g.len);
-    const int i = ok ? x : 0;
-    const int j = ok ? x + g.d : g.d0;
-    const uint32_t u = __float_as_uint(pair_key<NORM, MC>(sd.y, i, j, sd.m, sd.tau)) & 0x7FFFFFFFu;
-    const uint32_t r = rho_of(u, rc);
-    return ok ? r : rc.Kp;
 }
 
 // Line rank lambda_t: the smallest distinct-threshold index at which cell t
@@ -619,17 +799,18 @@ __device__ __forceinline__ uint32_t rho_at(const SeriesDesc& sd, const TileGeo& 
 // lmin consecutive cells containing t of the window's largest rho (cells
 // outside the diagonal have rho = Kp).  lmin = 2: max(rho_t, min(rho_{t-1},
 // rho_{t+1})).
-template <int NORM, int MC, int LMC>
+template <int NORM, int MC, int TC, int LMC>
 struct SweepBody {
     uint2* stab;          // LDS [RHO_TABLE]
     uint32_t* ses;        // LDS [RQA_MAX_K]
-    uint32_t* brho;       // LDS [Kcap][64]
-    uint32_t* blam;       // LDS [Kcap][64]
+    uint32_t* brho;       // LDS [Kcap+1][64]: row Kp collects cells that recur at no threshold
+    uint32_t* blam;       // LDS [Kcap+1][64]
     const uint2* rtab;    // global [S][RHO_TABLE]
     SeriesWork* works;
     uint32_t Kcap;
     RhoCtx rc;
     uint32_t lmin;
+    bool multi;
     bool active = true;
 
     __device__ void begin(uint32_t s)
@@ -637,13 +818,14 @@ struct SweepBody {
         const SeriesWork& w = works[s];
         for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RHO_TABLE + i];
         for (uint32_t i = threadIdx.x; i < RQA_MAX_K; i += blockDim.x) ses[i] = w.esorted[i];
-        for (uint32_t i = threadIdx.x; i < Kcap * TILE_W; i += blockDim.x) { brho[i] = 0u; blam[i] = 0u; }
+        for (uint32_t i = threadIdx.x; i < (Kcap + 1) * TILE_W; i += blockDim.x) { brho[i] = 0u; blam[i] = 0u; }
         rc.table = stab;
         rc.es = ses;
-        rc.emin = w.emin;
-        rc.emax = w.emax;
-        rc.shift = w.shift;
-        rc.Kp = w.Kp;
+        rc.emin = __uint_as_float(uniform(w.emin));
+        rc.emax = __uint_as_float(uniform(w.emax));
+        rc.shift = uniform(w.shift);
+        rc.Kp = uniform(w.Kp);
+        multi = uniform(w.multi) != 0;
     }
     __device__ void flush(uint32_t s)
     {
@@ -657,24 +839,77 @@ struct SweepBody {
                                (unsigned long long)sum);
         }
     }
-    __device__ __forceinline__ void emit(uint32_t rho, uint32_t lam, int lane)
+    // rho, lam <= Kp: the row Kp absorbs cells that recur at no threshold, so
+    // the counting is branch-free and every lane hits its own bank.
+    __device__ __forceinline__ void emit(uint32_t rho, uint32_t lam, int lane) const
     {
-        if (rho < rc.Kp) atomicAdd(&brho[rho * TILE_W + lane], 1u);
-        if (lam < rc.Kp) atomicAdd(&blam[lam * TILE_W + lane], 1u);
+        atomicAdd(&brho[rho * TILE_W + lane], 1u);
+        atomicAdd(&blam[lam * TILE_W + lane], 1u);
     }
-    __device__ void tile(const SeriesDesc& sd, uint32_t tile_id, int lane)
+    template <bool MULTI>
+    __device__ __forceinline__ uint32_t rho_at(const SeriesScalars& sd, const TileGeo& g, int x) const
+    {
+        const bool ok = (x >= 0) && (x < g.len);
+        const int i = ok ? x : 0;
+        const int j = ok ? x + g.d : g.d0;
+        const uint32_t r = rho_of<MULTI>(__float_as_uint(pair_key<NORM, MC, TC>(sd.y, i, j, sd.m, sd.tau)), rc);
+        return ok ? r : rc.Kp;
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        if (multi) tile_impl<true>(sd, tile_id, lane);
+        else tile_impl<false>(sd, tile_id, lane);
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void tile_impl(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
         const TileGeo g = tile_geo(sd, tile_id, lane);
+        constexpr bool kFast = (LMC == 1 || LMC == 2) && MC > 0 && (MC == 1 || TC > 0);
+        constexpr int TW = MC == 1 ? 1 : TC;
+        if constexpr (kFast) {
+            if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
+                // interior: every lane's diagonal covers [t0 - 1, t1 + WALK_SLACK]
+                const RhoCtx c = rc;
+                constexpr int HU = walk_block<NORM, MC, TW>();
+                if constexpr (LMC == 1) {
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                        uint32_t r[HU];
+#pragma unroll
+                        for (int u = 0; u < HU; ++u) r[u] = rho_of<MULTI>(k[u], c);
+#pragma unroll
+                        for (int u = 0; u < HU; ++u)
+                            if (u < valid) emit(r[u], r[u], lane);
+                    });
+                } else {
+                    uint32_t rm1 = rho_at<MULTI>(sd, g, g.t0 - 1);
+                    uint32_t r0 = rho_at<MULTI>(sd, g, g.t0);
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                        uint32_t r[HU];
+#pragma unroll
+                        for (int u = 0; u < HU; ++u) r[u] = rho_of<MULTI>(k[u], c);
+#pragma unroll
+                        for (int u = 0; u < HU; ++u) {
+                            if (u < valid) {
+                                emit(r0, max(r0, min(rm1, r[u])), lane);
+                                rm1 = r0;
+                                r0 = r[u];
+                            }
+                        }
+                    });
+                }
+                return;
+            }
+        }
         if constexpr (LMC == 1) {
             for (int x = g.t0; x < g.t1; ++x) {
-                const uint32_t r = rho_at<NORM, MC>(sd, g, x, rc);
+                const uint32_t r = rho_at<MULTI>(sd, g, x);
                 emit(r, r, lane);
             }
         } else if constexpr (LMC == 2) {
-            uint32_t rm1 = rho_at<NORM, MC>(sd, g, g.t0 - 1, rc);
-            uint32_t r0 = rho_at<NORM, MC>(sd, g, g.t0, rc);
+            uint32_t rm1 = rho_at<MULTI>(sd, g, g.t0 - 1);
+            uint32_t r0 = rho_at<MULTI>(sd, g, g.t0);
             for (int x = g.t0; x < g.t1; ++x) {
-                const uint32_t rp1 = rho_at<NORM, MC>(sd, g, x + 1, rc);
+                const uint32_t rp1 = rho_at<MULTI>(sd, g, x + 1);
                 emit(r0, max(r0, min(rm1, rp1)), lane);
                 rm1 = r0;
                 r0 = rp1;
@@ -687,7 +922,7 @@ struct SweepBody {
 #pragma unroll
             for (int i = 0; i < LMIN_MAX; ++i) { rr[i] = rc.Kp; ww[i] = rc.Kp; }
             for (int x = g.t0 - h; x < g.t1 + h; ++x) {
-                const uint32_t r = rho_at<NORM, MC>(sd, g, x, rc);
+                const uint32_t r = rho_at<MULTI>(sd, g, x);
 #pragma unroll
                 for (int i = 0; i < LMIN_MAX - 1; ++i) rr[i] = rr[i + 1];
                 rr[LMIN_MAX - 1] = r;
@@ -712,79 +947,63 @@ struct SweepBody {
     }
 };
 
-template <int NORM, int MC, int LMC>
+// LDS of the sweep: rank table, thresholds, two per-lane histograms with a
+// spare row, then the work-queue word.
+__host__ __device__ __forceinline__ size_t sweep_lds_bytes_dev(uint32_t Kcap)
+{
+    return RHO_TABLE * sizeof(uint2) + RQA_MAX_K * 4 + 2 * (size_t)(Kcap + 1) * TILE_W * 4;
+}
+
+template <int NORM, int MC, int TC, int LMC>
 __global__ void __launch_bounds__(512)
 k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
-        uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
-        uint32_t Kcap)
+        uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab, uint32_t Kcap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    SweepBody<NORM, MC, LMC> body;
+    SweepBody<NORM, MC, TC, LMC> body;
     body.stab = (uint2*)smem;
     body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
     body.brho = body.ses + RQA_MAX_K;
-    body.blam = body.brho + (size_t)Kcap * TILE_W;
+    body.blam = body.brho + (size_t)(Kcap + 1) * TILE_W;
     body.rtab = rtab;
     body.works = works;
     body.Kcap = Kcap;
-    body.lmin = 0;
-    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
+    body.multi = false;
+    // the generic line class reads lmin from the descriptors: launches group
+    // series of one lmin
+    body.lmin = LMC == 0 ? sds[0].lmin : (uint32_t)LMC;
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + sweep_lds_bytes_dev(Kcap)));
 }
 
-// The generic-lmin body needs the series' lmin; it is uniform per launch
-// because launches group series by variant, so read it from the first series.
-template <int NORM, int MC>
-__global__ void __launch_bounds__(512)
-k_sweep_lgen(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
-             uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
-             uint32_t Kcap)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    SweepBody<NORM, MC, 0> body;
-    body.stab = (uint2*)smem;
-    body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
-    body.brho = body.ses + RQA_MAX_K;
-    body.blam = body.brho + (size_t)Kcap * TILE_W;
-    body.rtab = rtab;
-    body.works = works;
-    body.Kcap = Kcap;
-    body.lmin = sds[0].lmin;
-    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body);
-}
+size_t sweep_lds_bytes(uint32_t Kcap) { return sweep_lds_bytes_dev(Kcap) + 16; }
 
-size_t sweep_lds_bytes(uint32_t Kcap)
-{
-    return RHO_TABLE * sizeof(uint2) + RQA_MAX_K * 4 + 2 * (size_t)Kcap * TILE_W * 4;
-}
+using SweepFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint2*,
+                         uint32_t);
 
-int variant_of(uint32_t norm, uint32_t m, uint32_t lmin)
-{
-    const int lc = (lmin == 1) ? 1 : (lmin == 2) ? 2 : 0;
-    return select_variant_of(norm, m) * 3 + lc;
-}
-
-using SweepFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*,
-                         const uint2*, uint32_t);
-
-template <int NORM, int MC>
+template <int NORM, int MC, int TC>
 static SweepFn sweep_fn_l(int lc)
 {
-    if (lc == 1) return k_sweep<NORM, MC, 1>;
-    if (lc == 2) return k_sweep<NORM, MC, 2>;
-    return k_sweep_lgen<NORM, MC>;
+    if (lc == 1) return k_sweep<NORM, MC, TC, 1>;
+    if (lc == 2) return k_sweep<NORM, MC, TC, 2>;
+    return k_sweep<NORM, MC, TC, 0>;
+}
+
+template <int NORM>
+static SweepFn sweep_fn_n(int mclass, int lc)
+{
+    switch (mclass) {
+    case 1: return sweep_fn_l<NORM, 1, 0>(lc);
+    case 2: return sweep_fn_l<NORM, 3, 3>(lc);
+    case 3: return sweep_fn_l<NORM, 3, 5>(lc);
+    default: return sweep_fn_l<NORM, 0, 0>(lc);
+    }
 }
 
 static SweepFn sweep_fn(int variant)
 {
-    const int lc = variant % 3;
-    switch (variant / 3) {
-    case 0: return sweep_fn_l<RQA_NORM_MAX, MC_ANY>(lc);
-    case 1: return sweep_fn_l<RQA_NORM_MAX, MC_1>(lc);
-    case 2: return sweep_fn_l<RQA_NORM_MAX, MC_3>(lc);
-    case 3: return sweep_fn_l<RQA_NORM_EUCLIDEAN, MC_ANY>(lc);
-    case 4: return sweep_fn_l<RQA_NORM_EUCLIDEAN, MC_1>(lc);
-    default: return sweep_fn_l<RQA_NORM_EUCLIDEAN, MC_3>(lc);
-    }
+    const int lc = variant % 3, sv = variant / 3;
+    const int norm = sv / NUM_MCLASS, mc = sv % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? sweep_fn_n<RQA_NORM_MAX>(mc, lc) : sweep_fn_n<RQA_NORM_EUCLIDEAN>(mc, lc);
 }
 
 hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, uint32_t grid, uint32_t block,
@@ -824,6 +1043,7 @@ __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict
         while (sh < 31 && (es[kp - 1] >> sh) - (es[0] >> sh) >= RHO_TABLE) ++sh;
         s_kp = kp;
         s_shift = sh;
+        w.multi = 0u;  // set before the barrier; table entries below may raise it
     }
     __syncthreads();
     const uint32_t kp = s_kp, sh = s_shift;
@@ -851,6 +1071,7 @@ __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict
             }
             e.x = inside ? es[below] : 0xFFFFFFFFu;
             e.y = (inside >= 2) ? (below | (inside << 16)) : below;
+            if (inside >= 2) w.multi = 1u;
         }
         tab[idx] = e;
     }
@@ -862,10 +1083,92 @@ hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------ sketch
+
+// SplitMix64 output for counter s of stream `seed` (Steele, Lea and Flood,
+// "Fast splittable pseudorandom number generators", OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t s)
+{
+    uint64_t z = seed + (s + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One workgroup per series: SKETCH_P pairs drawn uniformly (counter-based
+// SplitMix64, pair index v mod M in diagonal-major order), their keys sorted
+// in LDS, the median as scale, and the histogram of (bits - scale) >> 21
+// clamped to SKETCH_BINS quarter-binade bins.
+__global__ void __launch_bounds__(256) k_sketch(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                                float* __restrict__ features, uint32_t* __restrict__ sample_sorted)
+{
+    __shared__ uint32_t keys[SKETCH_P];
+    __shared__ uint32_t hist[SKETCH_BINS];
+    const uint32_t s = blockIdx.x;
+    const SeriesDesc& sd = sds[s];
+    const uint64_t M = sd.M;
+    const uint64_t L0 = (uint64_t)sd.nv - sd.w;
+    for (uint32_t i = threadIdx.x; i < SKETCH_BINS; i += blockDim.x) hist[i] = 0u;
+    for (uint32_t q = threadIdx.x; q < (uint32_t)SKETCH_P; q += blockDim.x) {
+        const uint64_t p = splitmix64(sd.seed, q) % M;
+        // diagonal offset dl: the largest with C(dl) = dl*L0 - dl(dl-1)/2 <= p
+        auto C = [&](uint64_t dl) { return dl * L0 - (dl * (dl - 1)) / 2; };
+        const double b = 2.0 * (double)L0 + 1.0;
+        const double disc = b * b - 8.0 * (double)p;
+        double est = 0.5 * (b - sqrt(disc > 0.0 ? disc : 0.0));
+        uint64_t dl = est > 0.0 ? (uint64_t)est : 0;
+        if (dl > L0 - 1) dl = L0 - 1;
+        while (dl > 0 && C(dl) > p) --dl;
+        while (dl + 1 < L0 && C(dl + 1) <= p) ++dl;
+        const int t = (int)(p - C(dl));
+        const int j = t + (int)sd.w + (int)dl;
+        const float key = sd.norm == RQA_NORM_MAX ? pair_key<RQA_NORM_MAX, 0, 0>(sd.y, t, j, sd.m, sd.tau)
+                                                  : pair_key<RQA_NORM_EUCLIDEAN, 0, 0>(sd.y, t, j, sd.m, sd.tau);
+        keys[q] = __float_as_uint(key);
+    }
+    __syncthreads();
+    // bitonic sort of the sampled key bits, ascending
+    for (uint32_t k = 2; k <= (uint32_t)SKETCH_P; k <<= 1) {
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = threadIdx.x; i < (uint32_t)SKETCH_P; i += blockDim.x) {
+                const uint32_t l = i ^ jj;
+                if (l > i) {
+                    const uint32_t a = keys[i], c = keys[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > c) == up) { keys[i] = c; keys[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t scale = keys[SKETCH_P / 2 - 1];
+    for (uint32_t q = threadIdx.x; q < (uint32_t)SKETCH_P; q += blockDim.x) {
+        int idx = (int)(((int64_t)keys[q] - (int64_t)scale) >> 21) + SKETCH_BINS / 2;
+        idx = min(max(idx, 0), SKETCH_BINS - 1);
+        atomicAdd(&hist[idx], 1u);
+        if (sample_sorted) sample_sorted[(size_t)s * SKETCH_P + q] = keys[q];
+    }
+    __syncthreads();
+    float* f = features + (size_t)s * SKETCH_FEATURES;
+    for (uint32_t i = threadIdx.x; i < SKETCH_BINS; i += blockDim.x) f[i] = (float)hist[i] * (1.0f / SKETCH_P);
+    if (threadIdx.x == 0) {
+        f[SKETCH_BINS] = sd.f_logn;
+        f[SKETCH_BINS + 1] = sd.f_m;
+        works[s].scale = scale;
+    }
+}
+
+hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint32_t* sample_sorted)
+{
+    hipLaunchKernelGGL(k_sketch, dim3(b.S), dim3(256), 0, st, b.sd, b.work, features, sample_sorted);
+    return hipGetLastError();
+}
+
 hipError_t set_kernel_lds_limits(size_t max_dyn_lds)
 {
     hipError_t err = hipSuccess;
-    for (int v = 0; v < 6; ++v) {
+    for (int v = 0; v < NUM_SELECT_VARIANTS; ++v) {
         for (int p = 1; p <= 3; ++p) {
             hipError_t e = hipFuncSetAttribute((const void*)select_fn_pass(p, v),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);

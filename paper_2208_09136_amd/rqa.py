@@ -58,6 +58,11 @@ SIGNATURES = {
     "rqa_set_timing": (_i32, [_vp, _i32]),
     "rqa_set_shape": (_i32, [_vp, _u32, _u32]),
     "rqa_set_grid": (_i32, [_vp, _u32]),
+    "rqa_autotune": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    "rqa_autotune_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, ctypes.POINTER(_u32)]),
+    "rqa_sketch_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _u64, _fp, ctypes.POINTER(_u32)]),
+    "rqa_tune_save": (_i32, [_vp, ctypes.c_char_p]),
+    "rqa_tune_load": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_status_string": (ctypes.c_char_p, [_i32]),
     "rqa_last_error": (ctypes.c_char_p, []),
 }
@@ -148,6 +153,55 @@ def rqa_set_shape(ctx, segment=0, chunk_tiles=0):
 
 def rqa_set_grid(ctx, workgroups=0):
     _check(load().rqa_set_grid(ctx, workgroups))
+
+
+def rqa_autotune(ctx, series, params, rr):
+    """Tune the launch shape on one series; returns (segment, chunk_tiles)."""
+    ptr, n = _series_ptr(series)
+    rrt = _a(rr, np.float64)
+    seg, chunk = _u32(0), _u32(0)
+    prm = _params(params)
+    _check(load().rqa_autotune(ctx, ptr, n, ctypes.byref(prm), _p(rrt, ctypes.c_double), len(rrt),
+                               ctypes.byref(seg), ctypes.byref(chunk)))
+    return seg.value, chunk.value
+
+
+def rqa_autotune_batch(ctx, concat, offsets, params, rr):
+    """Tune per-bucket segment lengths and the batch chunk size; returns the
+    chunk size."""
+    ptr, _ = _series_ptr(concat)
+    offs = _a(offsets, np.uint64)
+    S = len(offs) - 1
+    rrt = _a(rr, np.float64)
+    prm = (rqa_params * S)(*[_params(p) for p in params])
+    chunk = _u32(0)
+    _check(load().rqa_autotune_batch(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, _p(rrt, ctypes.c_double),
+                                     rrt.shape[1], ctypes.byref(chunk)))
+    return chunk.value
+
+
+SKETCH_FEATURES = 66
+
+
+def rqa_sketch_batch(ctx, concat, offsets, params, seed):
+    """Sketch features (S, 66) float32 and scales (S,) uint32 of S series."""
+    ptr, _ = _series_ptr(concat)
+    offs = _a(offsets, np.uint64)
+    S = len(offs) - 1
+    prm = (rqa_params * S)(*[_params(p) for p in params])
+    feats = np.zeros((S, SKETCH_FEATURES), np.float32)
+    scale = np.zeros(S, np.uint32)
+    _check(load().rqa_sketch_batch(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, int(seed),
+                                   _p(feats, ctypes.c_float), scale.ctypes.data_as(ctypes.POINTER(_u32))))
+    return feats, scale
+
+
+def rqa_tune_save(ctx, path):
+    _check(load().rqa_tune_save(ctx, os.fsencode(path)))
+
+
+def rqa_tune_load(ctx, path):
+    _check(load().rqa_tune_load(ctx, os.fsencode(path)))
 
 
 def rqa_select_thresholds(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
@@ -270,3 +324,18 @@ class Context:
 
     def set_grid(self, workgroups=0):
         rqa_set_grid(self.ctx, workgroups)
+
+    def autotune(self, series, params, rr):
+        return rqa_autotune(self.ctx, series, params, rr)
+
+    def autotune_batch(self, concat, offsets, params, rr):
+        return rqa_autotune_batch(self.ctx, concat, offsets, params, rr)
+
+    def sketch_batch(self, concat, offsets, params, seed):
+        return rqa_sketch_batch(self.ctx, concat, offsets, params, seed)
+
+    def tune_save(self, path):
+        rqa_tune_save(self.ctx, path)
+
+    def tune_load(self, path):
+        rqa_tune_load(self.ctx, path)

@@ -150,7 +150,7 @@ def test_segment_and_chunk_shapes(ctx, shape, n):
                 "rr": np.array(synth.RR_20)}
         check_case(ctx, case)
     finally:
-        ctx.set_shape(1024, 16)
+        ctx.set_shape(0, 0)
 
 
 @pytest.mark.parametrize("grid", [1, 7, 4096])
@@ -166,6 +166,31 @@ def test_more_workgroups_than_chunks(ctx, grid):
         check_case(ctx, case)
     finally:
         ctx.set_grid(0)
+
+
+def test_autotuned_shapes_keep_results(ctx, tmp_path):
+    """The autotuner only changes launch shapes: results after tuning (single
+    and batched), and after a save/load round trip of the table, equal the
+    oracle's / the untuned run's."""
+    case = synth.config_medium(n=3000)[12]
+    before = ctx.run(dev(case["y"]), prm(case), case["rr"])
+    seg, chunk = ctx.autotune(dev(case["y"]), prm(case), case["rr"])
+    assert seg % 64 == 0 and 64 <= seg <= 4096 and chunk in (2, 8, 32)
+    assert_run_equal(ctx.run(dev(case["y"]), prm(case), case["rr"]), before, "tuned")
+    cases = synth.config_batch(realisations=1)[1::3][:10]
+    ys = [c["y"] for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(y) for y in ys])]).astype(np.uint64)
+    concat = dev(np.concatenate(ys))
+    rr = np.stack([c["rr"] for c in cases])
+    plain = ctx.batch(concat, offs, [prm(c) for c in cases], rr)
+    ctx.autotune_batch(concat, offs, [prm(c) for c in cases], rr)
+    path = str(tmp_path / "tune.json")
+    ctx.tune_save(path)
+    ctx.tune_load(path)
+    tuned = ctx.batch(concat, offs, [prm(c) for c in cases], rr)
+    for key in ("eps", "count", "det", "det_mean"):
+        assert np.array_equal(tuned[key], plain[key]), key
+    assert_run_equal(ctx.run(dev(cases[0]["y"]), prm(cases[0]), cases[0]["rr"]), oracle_run(cases[0]), "tuned batch")
 
 
 def test_unsorted_and_repeated_targets(ctx):
@@ -291,3 +316,16 @@ def test_error_paths(ctx):
     assert e.value.name == "RQA_ERR_UNSUPPORTED"
     # the context still works after errors
     check_case(ctx, synth.config_small(0))
+
+
+# ---------------------------------------------------------------- sketch
+def test_sketch_matches_oracle(ctx):
+    from oracle import sketch
+    cases = [synth.config_small(0), synth.config_medium(n=2000)[12], synth.config_medium(n=3000)[3]]
+    ys = [c["y"] for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(y) for y in ys])]).astype(np.uint64)
+    feats, scale = ctx.sketch_batch(dev(np.concatenate(ys)), offs, [prm(c) for c in cases], seed=777)
+    for s, c in enumerate(cases):
+        f, sc = sketch.sketch(c["y"], c["m"], c["tau"], c["norm"], c["theiler"], seed=777 + s)
+        assert int(scale[s]) == sc
+        assert np.array_equal(feats[s], f)
