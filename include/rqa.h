@@ -75,9 +75,12 @@ typedef struct {
 
 /* flags */
 enum {
-    RQA_SEL_PLAIN = 0,   /* exact radix/histogram threshold selection */
-    RQA_SEL_LEARNED = 1, /* bracket from the loaded model, exact in-bracket resolution, plain fallback */
-    RQA_FULL_HIST = 2    /* reserved for the full line-length histogram: RQA_ERR_UNSUPPORTED */
+    RQA_SEL_PLAIN = 0,   /* exact selection: three radix passes over all pairs */
+    RQA_SEL_LEARNED = 1, /* exact selection inside a key window the network predicts (two passes);
+                            series with a target outside the window fall back to RQA_SEL_PLAIN */
+    RQA_FULL_HIST = 2,   /* reserved for the full line-length histogram: RQA_ERR_UNSUPPORTED */
+    RQA_SEL_SAMPLE = 4,  /* as RQA_SEL_LEARNED with the window from sketch-sample quantiles (no network) */
+    RQA_SEL_WINDOW = 8   /* as RQA_SEL_LEARNED with the window set by rqa_set_window (for tests) */
 };
 
 /* Create a context on HIP device `device`.  hip_stream is a hipStream_t on
@@ -90,7 +93,8 @@ rqa_status rqa_create(rqa_ctx **out, int device, void *hip_stream);
 void rqa_destroy(rqa_ctx *ctx);
 
 /* Exact thresholds for K target recurrence rates (Averaged RQA section: the
- * RR is preselected and eps follows from it).
+ * RR is preselected and eps follows from it).  Every selection method gives
+ * the same exact thresholds; they differ in the number of passes.
  *   series_dev: n float32 samples (device).
  *   rr: K targets in (0, 1] (host), any order, repeats allowed.
  *   flags: RQA_SEL_PLAIN or RQA_SEL_LEARNED.
@@ -182,6 +186,49 @@ rqa_status rqa_autotune_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev,
 #define RQA_SKETCH_FEATURES 66
 rqa_status rqa_sketch_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
                             const rqa_params *p, uint64_t seed, float *features_out, uint32_t *scale_out);
+
+/* Threshold-bracket network (an extension of the method; the paper has no
+ * learned part): a perceptron 66 -> 128 -> 128 -> 20 with exact GELU hidden
+ * layers mapping the sketch features to the offsets
+ * t_r = (bits(eps_r) - scale) / 2^23 of the exact thresholds of the 20 target
+ * rates 0.01, 0.02, ..., 0.20.  It is held by the context; its forward and
+ * backward passes and Adam run in the library's own FP32 kernels.
+ * Parameter layout (RQA_MLP_PARAMS floats): W1[66][128], b1[128],
+ * W2[128][128], b2[128], W3[128][20], b3[20], row-major. */
+#define RQA_MLP_INPUTS 66
+#define RQA_MLP_OUTPUTS 20
+#define RQA_MLP_PARAMS 27668
+/* He-uniform weights from the SplitMix64 stream `seed`, zero biases, Adam reset. */
+rqa_status rqa_mlp_init(rqa_ctx *ctx, uint64_t seed);
+/* Copy parameters in (host, count = RQA_MLP_PARAMS; Adam reset) or out. */
+rqa_status rqa_mlp_set_params(rqa_ctx *ctx, const float *params, uint64_t count);
+rqa_status rqa_mlp_get_params(rqa_ctx *ctx, float *params, uint64_t count);
+/* y_dev[B][20] = network(x_dev[B][66]); both device pointers, B <= 65536. */
+rqa_status rqa_mlp_forward(rqa_ctx *ctx, const float *x_dev, uint32_t B, float *y_dev);
+/* Gradient of the mean squared error against t_dev[B][20] (device) with
+ * respect to the parameters, into grad_out (host, RQA_MLP_PARAMS floats);
+ * loss_out (or NULL) receives the loss.  Parameters are unchanged. */
+rqa_status rqa_mlp_gradients(rqa_ctx *ctx, const float *x_dev, const float *t_dev, uint32_t B,
+                             float *grad_out, double *loss_out);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr on the
+ * batch; loss_out (or NULL) receives the loss before the step. */
+rqa_status rqa_mlp_train_step(rqa_ctx *ctx, const float *x_dev, const float *t_dev, uint32_t B, float lr,
+                              double *loss_out);
+/* Half-widths (RQA_MLP_OUTPUTS, offset units) of the bracket around each
+ * predicted offset, from calibration on held-out series. */
+rqa_status rqa_mlp_set_bracket(rqa_ctx *ctx, const float *delta, uint32_t n);
+
+/* Window of the RQA_SEL_WINDOW method: key values [lo, hi] (>= 0, not NaN). */
+rqa_status rqa_set_window(rqa_ctx *ctx, float lo, float hi);
+/* Width z of the RQA_SEL_SAMPLE window: sample ranks q P -/+ z sqrt(P q (1-q))
+ * around each target rate q (default 5). */
+rqa_status rqa_set_sample_width(rqa_ctx *ctx, float z);
+/* Statistics of the last selection on this context: full counting passes
+ * over all pairs (3 plain, 2 windowed, 5 windowed with fallback), series
+ * that fell back to plain selection, targets outside their window.  Any
+ * pointer may be NULL. */
+rqa_status rqa_selection_stats(rqa_ctx *ctx, uint32_t *full_passes, uint32_t *series_fallback,
+                               uint32_t *targets_missed);
 
 /* Save / load the context's autotuned table as JSON (path: host string).
  * Loading replaces the table; a malformed file leaves it unchanged. */

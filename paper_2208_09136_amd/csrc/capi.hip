@@ -80,6 +80,11 @@ struct rqa_ctx {
     float* mlp_partial = nullptr;
     uint64_t adam_t = 0;
     bool has_model = false;
+    float sample_z = 5.0f;       // width of the sample-quantile window in standard deviations
+    uint32_t win_lo = 0, win_hi = 0x7F800000u;  // caller-given window (RQA_SEL_WINDOW)
+    // statistics of the last selection: full counting passes over all pairs,
+    // series that fell back to the plain path, targets outside their window
+    uint32_t stat_passes = 0, stat_fallback = 0, stat_missed = 0;
     float bracket_delta[MLP_OUT] = {};  // calibrated half-widths of the bracket (offset units)
     // device pool
     void* pool = nullptr;
@@ -253,6 +258,7 @@ struct Job {
     uint32_t K = 0;
     int mode = MODE_BOTH;
     uint64_t seed = 0;               // sketch stream of series 0 (series s uses seed + s)
+    int sel = 0;                     // selection: 0 plain radix, 1 network window, 2 sample window, 3 given window
     std::vector<uint64_t> k;         // S*K, selection targets
     std::vector<uint32_t> eps_bits;  // S*K, sweep-only thresholds
     // results
@@ -262,7 +268,10 @@ struct Job {
     std::vector<uint64_t> M;
     std::vector<float> features;     // S*SKETCH_FEATURES (sketch mode)
     std::vector<uint32_t> scale;     // S (sketch mode)
+    std::vector<uint8_t> hit;        // S*K, window selection: target resolved in the window
 };
+
+rqa_status ensure_acts(rqa_ctx* c, uint32_t B, MlpActs& a);
 
 // Runs selection and/or sweep for every series of the job.
 rqa_status run_job(rqa_ctx* c, Job& job)
@@ -348,11 +357,19 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_h1 = carve(sizeof(uint64_t) * S * SEL_N1);
     const size_t o_h2 = carve(sizeof(uint64_t) * S * K * SEL_N2);
     const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
+    const bool window = (job.mode & MODE_SELECT) && job.sel != 0;
+    const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
     const size_t zero_end = off;  // tickets and histograms are cleared every call
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
     const size_t o_rt = carve(sizeof(uint2) * S * RHO_TABLE);
-    const size_t o_feat = (job.mode & MODE_SKETCH) ? carve(sizeof(float) * S * SKETCH_FEATURES) : 0;
+    const bool sketch = (job.mode & MODE_SKETCH) || window;
+    const size_t o_feat = sketch ? carve(sizeof(float) * S * SKETCH_FEATURES) : 0;
+    const size_t o_smp = window ? carve(sizeof(uint32_t) * S * SKETCH_P) : 0;
+    const size_t o_wtab = window ? carve((size_t)S * WIN_BINS) : 0;
+    const size_t o_wfine = window ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
+    const size_t o_pred = window ? carve(sizeof(float) * S * MLP_OUT) : 0;
+    const size_t o_delta = window ? carve(sizeof(float) * MLP_OUT) : 0;
     rqa_status st = ensure_pool(c, off);
     if (st) return st;
     char* pool = (char*)c->pool;
@@ -374,12 +391,16 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     // host staging: descriptors + work (in), work (out), sketch features (out)
     const size_t hs_sd = sizeof(SeriesDesc) * S, hs_work = sizeof(SeriesWork) * S;
     const size_t hs_feat = (job.mode & MODE_SKETCH) ? sizeof(float) * S * SKETCH_FEATURES : 0;
-    st = ensure_host(c, hs_sd + 2 * hs_work + hs_feat);
+    st = ensure_host(c, hs_sd + 2 * hs_work + hs_feat + sizeof(float) * MLP_OUT);
     if (st) return st;
     SeriesDesc* h_sd = (SeriesDesc*)c->host;
     SeriesWork* h_work = (SeriesWork*)((char*)c->host + hs_sd);
     SeriesWork* h_out = (SeriesWork*)((char*)c->host + hs_sd + hs_work);
     float* h_feat = (float*)((char*)c->host + hs_sd + 2 * hs_work);
+    float* h_delta = (float*)((char*)c->host + hs_sd + 2 * hs_work + hs_feat);
+    std::memcpy(h_delta, c->bracket_delta, sizeof(float) * MLP_OUT);
+    if (window && job.sel == 1 && !c->has_model)
+        return fail(RQA_ERR_INVALID_ARG, "RQA_SEL_LEARNED needs a network (rqa_mlp_init / rqa_mlp_set_params)");
     std::memcpy(h_sd, sd.data(), hs_sd);
     std::memset(h_work, 0, hs_work);
     for (uint32_t i = 0; i < S; ++i) {
@@ -397,7 +418,21 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     HIP_TRY(hipMemcpyAsync(all.work, h_work, hs_work, hipMemcpyHostToDevice, sm));
     HIP_TRY(launch_zero(sm, pool + o_tick, zero_end - o_tick));
     HIP_TRY(launch_check_finite(sm, all, maxn));
-    if (job.mode & MODE_SKETCH) HIP_TRY(launch_sketch(sm, all, (float*)(pool + o_feat), nullptr));
+    if (sketch)
+        HIP_TRY(launch_sketch(sm, all, (float*)(pool + o_feat), window ? (uint32_t*)(pool + o_smp) : nullptr));
+    if (window) {
+        HIP_TRY(hipMemcpyAsync(pool + o_delta, h_delta, sizeof(float) * MLP_OUT, hipMemcpyHostToDevice, sm));
+        if (job.sel == 3) {
+            HIP_TRY(launch_window_fixed(sm, all, c->win_lo, c->win_hi));
+        } else if (job.sel == 1) {
+            MlpActs acts;
+            if ((st = ensure_acts(c, S, acts))) return st;
+            HIP_TRY(mlp_forward(sm, c->mlp, (const float*)(pool + o_feat), (int)S, acts, (float*)(pool + o_pred)));
+            HIP_TRY(launch_window_from_offsets(sm, all, (const float*)(pool + o_pred), (const float*)(pool + o_delta)));
+        } else {
+            HIP_TRY(launch_window_from_sample(sm, all, (const uint32_t*)(pool + o_smp), nullptr, c->sample_z));
+        }
+    }
     HIP_TRY(tm.end());
 
     auto view = [&](const Group& g) {
@@ -423,7 +458,33 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         return t;
     };
 
-    if (job.mode & MODE_SELECT) {
+    if (window) {
+        WinBufs wb;
+        wb.bins = (uint64_t*)(pool + o_wbins);
+        wb.table = (uint8_t*)(pool + o_wtab);
+        wb.fine = (uint64_t*)(pool + o_wfine);
+        for (int pass = 1; pass <= 2; ++pass) {
+            HIP_TRY(tm.begin(pass - 1));
+            for (const Group& g : groups) {
+                DevBufs v = view(g);
+                WinBufs wv = wb;
+                wv.bins = wb.bins + (size_t)g.begin * WIN_BINS;
+                wv.table = wb.table + (size_t)g.begin * WIN_BINS;
+                wv.fine = wb.fine + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
+                const uint32_t block = 512;
+                const int per_cu = window_blocks_per_cu(pass, g.sel, block);
+                const uint32_t grid = c->grid ? c->grid
+                                              : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
+                const int t = take(1);
+                if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
+                HIP_TRY(launch_window_pass(sm, v, wv, pass, g.sel, grid, block, (uint32_t)t));
+            }
+            HIP_TRY(tm.end());
+            HIP_TRY(tm.begin(PH_OTHER));
+            HIP_TRY(launch_window_scan(sm, all, wb, pass));
+            HIP_TRY(tm.end());
+        }
+    } else if (job.mode & MODE_SELECT) {
         for (int pass = 1; pass <= 3; ++pass) {
             HIP_TRY(tm.begin(pass - 1));
             for (const Group& g : groups) {
@@ -489,11 +550,12 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         job.features.assign((size_t)S * SKETCH_FEATURES, 0.f);
         job.scale.assign(S, 0);
     }
+    if (window) job.hit.assign((size_t)S * K, 0);
     for (uint32_t i = 0; i < S; ++i) {
         const uint32_t s = order[i];
         const SeriesWork& w = h_out[i];
         if (w.nonfinite) return fail(RQA_ERR_NONFINITE, "series %u holds a NaN or infinite sample", s);
-        if (w.status) return fail(RQA_ERR_DEVICE, "selection of series %u is inconsistent (code %u)", s, w.status);
+        if (w.status & ~8u) return fail(RQA_ERR_DEVICE, "selection of series %u is inconsistent (code %u)", s, w.status);
         if (job.mode & MODE_SKETCH) {
             std::memcpy(&job.features[(size_t)s * SKETCH_FEATURES], h_feat + (size_t)i * SKETCH_FEATURES,
                         sizeof(float) * SKETCH_FEATURES);
@@ -505,6 +567,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             job.eps[(size_t)s * K + r] = e;
             job.kout[(size_t)s * K + r] = w.k[r];
             job.count_sel[(size_t)s * K + r] = w.count[r];
+            if (window) job.hit[(size_t)s * K + r] = w.win_hit[r] ? 1 : 0;
         }
         if (job.mode & MODE_SWEEP) {
             const uint32_t Kp = w.Kp;
@@ -545,11 +608,14 @@ rqa_status check_k(uint32_t K)
     return RQA_OK;
 }
 
-rqa_status check_flags_select(uint32_t flags)
+rqa_status check_flags_select(uint32_t flags, int* sel)
 {
-    if (flags & ~(uint32_t)(RQA_SEL_LEARNED | RQA_FULL_HIST)) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const uint32_t known = RQA_SEL_LEARNED | RQA_FULL_HIST | RQA_SEL_SAMPLE | RQA_SEL_WINDOW;
+    if (flags & ~known) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     if (flags & RQA_FULL_HIST) return fail(RQA_ERR_UNSUPPORTED, "RQA_FULL_HIST is not implemented");
-    if (flags & RQA_SEL_LEARNED) return fail(RQA_ERR_UNSUPPORTED, "no threshold model is loaded");
+    const uint32_t m = flags & (RQA_SEL_LEARNED | RQA_SEL_SAMPLE | RQA_SEL_WINDOW);
+    if (m & (m - 1)) return fail(RQA_ERR_INVALID_ARG, "choose one selection method");
+    *sel = (m == RQA_SEL_LEARNED) ? 1 : (m == RQA_SEL_SAMPLE) ? 2 : (m == RQA_SEL_WINDOW) ? 3 : 0;
     return RQA_OK;
 }
 
@@ -598,6 +664,76 @@ rqa_status single_job(rqa_ctx* c, Job& job, const float* series, uint64_t n, con
             if ((st = check_eps(eps[r], &job.eps_bits[r]))) return st;
     }
     return run_job(c, job);
+}
+
+// Exact thresholds by the window method; every series with a target outside
+// its window (or without a usable window) is selected again by the plain
+// radix passes.  Leaves job.eps / kout / count_sel complete.
+rqa_status select_windowed(rqa_ctx* c, Job& job)
+{
+    const uint32_t S = (uint32_t)job.series.size(), K = job.K;
+    job.mode = MODE_SELECT;
+    rqa_status st = run_job(c, job);
+    if (st) return st;
+    std::vector<uint32_t> redo;
+    uint32_t missed = 0;
+    for (uint32_t s = 0; s < S; ++s) {
+        uint32_t m = 0;
+        for (uint32_t r = 0; r < K; ++r) m += job.hit[(size_t)s * K + r] ? 0 : 1;
+        missed += m;
+        if (m) redo.push_back(s);
+    }
+    c->stat_passes = 2;
+    c->stat_fallback = (uint32_t)redo.size();
+    c->stat_missed = missed;
+    if (redo.empty()) return RQA_OK;
+    Job plain;
+    plain.base = job.base;
+    plain.K = K;
+    plain.mode = MODE_SELECT;
+    for (uint32_t s : redo) {
+        plain.series.push_back(job.series[s]);
+        plain.k.insert(plain.k.end(), job.k.begin() + (size_t)s * K, job.k.begin() + (size_t)(s + 1) * K);
+    }
+    if ((st = run_job(c, plain))) return st;
+    for (size_t i = 0; i < redo.size(); ++i)
+        for (uint32_t r = 0; r < K; ++r) {
+            const size_t a = (size_t)redo[i] * K + r, b = i * K + r;
+            job.eps[a] = plain.eps[b];
+            job.kout[a] = plain.kout[b];
+            job.count_sel[a] = plain.count_sel[b];
+        }
+    c->stat_passes += 3;
+    return RQA_OK;
+}
+
+// Selection (plain or windowed) followed by the sweep at the selected
+// thresholds; plain selection and sweep share one job.
+rqa_status select_and_sweep(rqa_ctx* c, Job& job)
+{
+    if (job.sel == 0) {
+        job.mode = MODE_BOTH;
+        c->stat_passes = 3;
+        c->stat_fallback = 0;
+        c->stat_missed = 0;
+        return run_job(c, job);
+    }
+    rqa_status st = select_windowed(c, job);
+    if (st) return st;
+    Job sw;
+    sw.base = job.base;
+    sw.K = job.K;
+    sw.mode = MODE_SWEEP;
+    sw.series = job.series;
+    sw.eps_bits.resize(job.eps.size());
+    std::memcpy(sw.eps_bits.data(), job.eps.data(), sizeof(uint32_t) * job.eps.size());
+    if ((st = run_job(c, sw))) return st;
+    job.count = sw.count;
+    job.rr = sw.rr;
+    job.det = sw.det;
+    job.det_mean = sw.det_mean;
+    job.M = sw.M;
+    return RQA_OK;
 }
 
 rqa_status build_batch_job(Job& job, uint32_t S, const float* concat, const uint64_t* offsets, const rqa_params* p,
@@ -822,11 +958,22 @@ rqa_status rqa_select_thresholds(rqa_ctx* c, const float* series, uint64_t n, co
                                  const double* rr, uint32_t K, uint32_t flags, float* eps_out,
                                  uint64_t* k_out, uint64_t* count_out)
 {
-    rqa_status st = check_flags_select(flags);
+    int sel = 0;
+    rqa_status st = check_flags_select(flags, &sel);
     if (st) return st;
     if (!eps_out) return fail(RQA_ERR_INVALID_ARG, "eps_out is NULL");
     Job job;
-    if ((st = single_job(c, job, series, n, p, rr, nullptr, K, MODE_SELECT))) return st;
+    if ((st = single_job_setup(c, job, series, n, p, rr, K))) return st;
+    job.sel = sel;
+    job.mode = MODE_SELECT;
+    if (sel) {
+        if ((st = select_windowed(c, job))) return st;
+    } else {
+        c->stat_passes = 3;
+        c->stat_fallback = 0;
+        c->stat_missed = 0;
+        if ((st = run_job(c, job))) return st;
+    }
     for (uint32_t r = 0; r < K; ++r) {
         eps_out[r] = job.eps[r];
         if (k_out) k_out[r] = job.kout[r];
@@ -859,11 +1006,14 @@ rqa_status rqa_run(rqa_ctx* c, const float* series, uint64_t n, const rqa_params
                    uint32_t flags, float* eps_out, uint64_t* k_out, uint64_t* count_out, double* rr_out,
                    double* det_out, double* det_mean_out)
 {
-    rqa_status st = check_flags_select(flags);
+    int sel = 0;
+    rqa_status st = check_flags_select(flags, &sel);
     if (st) return st;
     if (!det_mean_out) return fail(RQA_ERR_INVALID_ARG, "det_mean_out is NULL");
     Job job;
-    if ((st = single_job(c, job, series, n, p, rr, nullptr, K, MODE_BOTH))) return st;
+    if ((st = single_job_setup(c, job, series, n, p, rr, K))) return st;
+    job.sel = sel;
+    if ((st = select_and_sweep(c, job))) return st;
     for (uint32_t r = 0; r < K; ++r) {
         if (eps_out) eps_out[r] = job.eps[r];
         if (k_out) k_out[r] = job.kout[r];
@@ -881,11 +1031,13 @@ rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t
 {
     rqa_status st = check_ctx(c);
     if (st) return st;
-    if ((st = check_flags_select(flags))) return st;
+    int sel = 0;
+    if ((st = check_flags_select(flags, &sel))) return st;
     if (!eps_out || !rr_out || !det_out || !det_mean_out) return fail(RQA_ERR_INVALID_ARG, "an output is NULL");
     Job job;
     if ((st = build_batch_job(job, S, concat, offsets, p, rr, K))) return st;
-    if ((st = run_job(c, job))) return st;
+    job.sel = sel;
+    if ((st = select_and_sweep(c, job))) return st;
     for (size_t i = 0; i < (size_t)S * K; ++i) {
         eps_out[i] = job.eps[i];
         rr_out[i] = job.rr[i];
@@ -935,6 +1087,35 @@ rqa_status rqa_sketch_batch(rqa_ctx* c, uint32_t S, const float* concat, const u
     if ((st = run_job(c, job))) return st;
     std::memcpy(features_out, job.features.data(), sizeof(float) * job.features.size());
     if (scale_out) std::memcpy(scale_out, job.scale.data(), sizeof(uint32_t) * S);
+    return RQA_OK;
+}
+
+rqa_status rqa_set_window(rqa_ctx* c, float lo, float hi)
+{
+    if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
+    uint32_t a, b;
+    rqa_status st;
+    if ((st = check_eps(lo, &a)) || (st = check_eps(hi, &b))) return st;
+    if (b < a) return fail(RQA_ERR_INVALID_ARG, "window upper end below lower end");
+    c->win_lo = a;
+    c->win_hi = b;
+    return RQA_OK;
+}
+
+rqa_status rqa_set_sample_width(rqa_ctx* c, float z)
+{
+    if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
+    if (!(z > 0.f) || !std::isfinite(z)) return fail(RQA_ERR_INVALID_ARG, "width must be positive");
+    c->sample_z = z;
+    return RQA_OK;
+}
+
+rqa_status rqa_selection_stats(rqa_ctx* c, uint32_t* full_passes, uint32_t* series_fallback, uint32_t* targets_missed)
+{
+    if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");
+    if (full_passes) *full_passes = c->stat_passes;
+    if (series_fallback) *series_fallback = c->stat_fallback;
+    if (targets_missed) *targets_missed = c->stat_missed;
     return RQA_OK;
 }
 

@@ -82,7 +82,22 @@ struct SeriesWork {
     uint32_t nonfinite;           // set when a sample is NaN or infinite
     uint32_t status;              // device-side error bits (0 = fine)
     uint32_t scale;               // sketch: bit pattern of the sample median
+    // window selection (learned or sampled bracket)
+    uint32_t win_lo, win_span;    // window [win_lo, win_lo + win_span] of key bit patterns
+    uint32_t win_shift, win_ok;   // fine-bin width 2^win_shift; win_ok = 0: no usable window
+    uint64_t win_below;           // #{key < win_lo}
+    uint32_t win_hit[RQA_MAX_K];  // target resolved inside the window
+    uint32_t win_fbin[RQA_MAX_K]; // fine bin of the target's key
+    uint32_t win_slot[RQA_MAX_K]; // pass-2 slot of that fine bin
+    uint64_t win_base[RQA_MAX_K]; // #{key < start of the fine bin}
+    uint32_t win_nslots;
 };
+
+// Window selection: WIN_BINS fine bins over the window; the last
+// win_shift <= WIN_MAX_SHIFT bits are resolved in a second pass.
+constexpr int WIN_BITS = 14;
+constexpr uint32_t WIN_BINS = 1u << WIN_BITS;
+constexpr uint32_t WIN_MAX_SHIFT = 14;
 
 // Device buffers of one call (host-side handle).
 struct DevBufs {
@@ -112,6 +127,23 @@ hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass);
 hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b);
 hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, uint32_t grid,
                         uint32_t block, uint32_t ticket);
+// Window selection.  Sources of the window: predicted offsets [S][20] with
+// half-widths (network), or the sorted sketch sample (sample quantiles).
+struct WinBufs {
+    uint64_t* bins;      // [S][WIN_BINS] pass-1 counts
+    uint8_t* table;      // [S][WIN_BINS] fine bin -> pass-2 slot
+    uint64_t* fine;      // [S][K][1 << WIN_MAX_SHIFT] pass-2 counts
+};
+hipError_t launch_window_from_offsets(hipStream_t st, const DevBufs& b, const float* pred, const float* delta_dev);
+hipError_t launch_window_fixed(hipStream_t st, const DevBufs& b, uint32_t lo, uint32_t hi);
+hipError_t launch_window_from_sample(hipStream_t st, const DevBufs& b, const uint32_t* sample_sorted, const double* rr_dev,
+                                     float z);
+hipError_t launch_window_pass(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass, int variant, uint32_t grid,
+                              uint32_t block, uint32_t ticket);
+hipError_t launch_window_scan(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass);
+size_t window_lds_bytes(int pass);
+int window_blocks_per_cu(int pass, int variant, uint32_t block);
+
 // Sketch of every series: features [S][SKETCH_FEATURES], sorted sample bits
 // [S][SKETCH_P] (may be NULL), scale into SeriesWork.
 hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint32_t* sample_sorted);

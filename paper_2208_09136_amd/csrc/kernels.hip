@@ -1084,6 +1084,382 @@ hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
 }
 
 
+// ------------------------------------------------------------------ window selection
+
+// Window of key bit patterns [lo, hi] (clamped to [0, +inf]) -> the smallest
+// fine-bin shift that covers it with WIN_BINS bins; unusable if the shift
+// exceeds WIN_MAX_SHIFT.
+__device__ void set_window(SeriesWork& w, int64_t lo, int64_t hi, bool valid)
+{
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > 0x7F800000ll ? 0x7F800000ll : hi;
+    w.win_below = 0;
+    w.win_nslots = 0;
+    if (!valid || hi < lo) {
+        w.win_ok = 0u;
+        w.win_lo = 0u;
+        w.win_span = 0u;
+        w.win_shift = 0u;
+        return;
+    }
+    const uint32_t span = (uint32_t)(hi - lo);
+    uint32_t sh = 0;
+    while (sh < 31 && (span >> sh) >= WIN_BINS) ++sh;
+    w.win_lo = (uint32_t)lo;
+    w.win_span = span;
+    w.win_shift = sh;
+    w.win_ok = sh <= WIN_MAX_SHIFT ? 1u : 0u;
+}
+
+// Window from predicted offsets t_r (network output) and half-widths d_r:
+// [scale + (t_r - d_r) 2^23, scale + (t_r + d_r) 2^23] over all outputs.
+__global__ void k_window_from_offsets(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works, uint32_t S,
+                                      const float* __restrict__ pred, const float* __restrict__ delta, int nout)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    SeriesWork& w = works[s];
+    const double sc = (double)w.scale;
+    double lo = 1e300, hi = -1e300;
+    bool valid = true;
+    for (int r = 0; r < nout; ++r) {
+        const double t = pred[(size_t)s * nout + r], d = delta[r];
+        valid &= isfinite(t);
+        lo = fmin(lo, sc + floor((t - d) * 8388608.0));
+        hi = fmax(hi, sc + ceil((t + d) * 8388608.0));
+    }
+    valid &= lo > -4.0e9 && hi < 4.0e9;
+    set_window(w, valid ? (int64_t)lo : 0, valid ? (int64_t)hi : -1, valid);
+}
+
+// Window from the sorted sketch sample: for each target rate q = k/M, the
+// sample keys at ranks q P -/+ z sqrt(P q (1 - q)) (one more below), over
+// all targets.
+__global__ void k_window_from_sample(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works, uint32_t S,
+                                     const uint32_t* __restrict__ sample, float z)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    SeriesWork& w = works[s];
+    const uint32_t* smp = sample + (size_t)s * SKETCH_P;
+    int64_t lo = 0x7F800000ll, hi = 0;
+    for (uint32_t r = 0; r < sds[s].K; ++r) {
+        const double q = (double)w.k[r] / (double)sds[s].M;
+        const double c = q * SKETCH_P, sd = sqrt(SKETCH_P * q * (1.0 - q)) * z;
+        const int ilo = (int)floor(c - sd) - 1, ihi = (int)ceil(c + sd);
+        lo = min(lo, ilo < 0 ? (int64_t)0 : (int64_t)smp[ilo]);
+        hi = max(hi, ihi >= SKETCH_P ? (int64_t)0x7F800000ll : (int64_t)smp[ihi]);
+    }
+    set_window(w, lo, hi, true);
+}
+
+// A window given by the caller, the same for every series.
+__global__ void k_window_fixed(SeriesWork* __restrict__ works, uint32_t S, uint32_t lo, uint32_t hi)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) set_window(works[s], (int64_t)lo, (int64_t)hi, true);
+}
+
+hipError_t launch_window_fixed(hipStream_t st, const DevBufs& b, uint32_t lo, uint32_t hi)
+{
+    hipLaunchKernelGGL(k_window_fixed, dim3((b.S + 63) / 64), dim3(64), 0, st, b.work, b.S, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_from_offsets(hipStream_t st, const DevBufs& b, const float* pred, const float* delta_dev)
+{
+    hipLaunchKernelGGL(k_window_from_offsets, dim3((b.S + 63) / 64), dim3(64), 0, st, b.sd, b.work, b.S, pred, delta_dev,
+                       20);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_from_sample(hipStream_t st, const DevBufs& b, const uint32_t* sample_sorted, const double*,
+                                     float z)
+{
+    hipLaunchKernelGGL(k_window_from_sample, dim3((b.S + 63) / 64), dim3(64), 0, st, b.sd, b.work, b.S, sample_sorted, z);
+    return hipGetLastError();
+}
+
+// Window pass 1: count keys below the window and histogram the window in
+// WIN_BINS fine bins.
+template <int NORM, int MC, int TC>
+struct WinPass1 {
+    uint32_t* bins;       // LDS [WIN_BINS]
+    uint64_t* gbins;      // global [S][WIN_BINS]
+    SeriesWork* works;
+    uint32_t lo, span, shift;
+    uint32_t below = 0;   // per lane
+    bool active = true;
+    __device__ void begin(uint32_t s)
+    {
+        const SeriesWork& w = works[s];
+        lo = uniform(w.win_lo);
+        span = uniform(w.win_span);
+        shift = uniform(w.win_shift);
+        active = uniform(w.win_ok) != 0;
+        below = 0;
+        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) bins[i] = 0u;
+    }
+    __device__ void flush(uint32_t s)
+    {
+        if (!active) return;
+        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) {
+            const uint32_t v = bins[i];
+            if (v) atomicAdd((unsigned long long*)&gbins[(size_t)s * WIN_BINS + i], (unsigned long long)v);
+        }
+        if (below) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)below);
+        below = 0;
+    }
+    __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
+    __device__ __forceinline__ void count(uint32_t u, uint32_t)
+    {
+        const uint32_t rel = u - lo;
+        below += u < lo ? 1u : 0u;
+        if (rel <= span) atomicAdd(&bins[rel >> shift], 1u);
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+    }
+};
+
+// Window pass 2: keys in a target's fine bin add to that bin's 2^shift
+// sub-bins in global memory (few keys qualify).
+template <int NORM, int MC, int TC>
+struct WinPass2 {
+    uint8_t* table;       // LDS [WIN_BINS] fine bin -> slot
+    const uint8_t* gtable;
+    uint64_t* fine;       // global [S][K][1 << WIN_MAX_SHIFT]
+    SeriesWork* works;
+    uint32_t K;
+    uint32_t lo, span, shift;
+    unsigned long long* dst;
+    bool active = true;
+    __device__ void begin(uint32_t s)
+    {
+        const SeriesWork& w = works[s];
+        lo = uniform(w.win_lo);
+        span = uniform(w.win_span);
+        shift = uniform(w.win_shift);
+        active = uniform(w.win_ok) != 0 && uniform(w.win_nslots) != 0;
+        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) table[i] = gtable[(size_t)s * WIN_BINS + i];
+        dst = (unsigned long long*)(fine + (size_t)s * K * (1u << WIN_MAX_SHIFT));
+    }
+    __device__ void flush(uint32_t) {}
+    __device__ __forceinline__ uint32_t look(uint32_t u) const
+    {
+        const uint32_t rel = u - lo;
+        const uint32_t fb = min(rel >> shift, WIN_BINS - 1);
+        const uint32_t sl = table[fb];
+        return rel <= span ? sl : (uint32_t)NO_SLOT;
+    }
+    __device__ __forceinline__ void count(uint32_t u, uint32_t sl) const
+    {
+        const uint32_t sub = (u - lo) & ((1u << shift) - 1u);
+        wave_add(dst, sl * (1u << WIN_MAX_SHIFT) + sub, sl != NO_SLOT);
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+    }
+};
+
+__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass) { return (pass == 1 ? WIN_BINS * 4 : WIN_BINS) + 16; }
+
+size_t window_lds_bytes(int pass) { return window_lds_bytes_dev(pass); }
+
+template <int PASS, int NORM, int MC, int TC>
+__global__ void __launch_bounds__(1024)
+k_window(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
+         uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, uint64_t* __restrict__ bins,
+         const uint8_t* __restrict__ table, uint64_t* __restrict__ fine, uint32_t K)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* slot = (uint32_t*)(smem + window_lds_bytes_dev(PASS) - 16);
+    if constexpr (PASS == 1) {
+        WinPass1<NORM, MC, TC> body;
+        body.bins = (uint32_t*)smem;
+        body.gbins = bins;
+        body.works = works;
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
+    } else {
+        WinPass2<NORM, MC, TC> body;
+        body.table = (uint8_t*)smem;
+        body.gtable = table;
+        body.fine = fine;
+        body.works = works;
+        body.K = K;
+        body.dst = nullptr;
+        chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
+    }
+}
+
+using WinFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, uint64_t*,
+                       const uint8_t*, uint64_t*, uint32_t);
+
+template <int PASS, int NORM>
+static WinFn window_fn_n(int mclass)
+{
+    switch (mclass) {
+    case 1: return k_window<PASS, NORM, 1, 0>;
+    case 2: return k_window<PASS, NORM, 3, 3>;
+    case 3: return k_window<PASS, NORM, 3, 5>;
+    default: return k_window<PASS, NORM, 0, 0>;
+    }
+}
+
+static WinFn window_fn(int pass, int variant)
+{
+    const int norm = variant / NUM_MCLASS, mc = variant % NUM_MCLASS;
+    if (pass == 1)
+        return norm == RQA_NORM_MAX ? window_fn_n<1, RQA_NORM_MAX>(mc) : window_fn_n<1, RQA_NORM_EUCLIDEAN>(mc);
+    return norm == RQA_NORM_MAX ? window_fn_n<2, RQA_NORM_MAX>(mc) : window_fn_n<2, RQA_NORM_EUCLIDEAN>(mc);
+}
+
+hipError_t launch_window_pass(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass, int variant, uint32_t grid,
+                              uint32_t block, uint32_t ticket)
+{
+    hipLaunchKernelGGL(window_fn(pass, variant), dim3(grid), dim3(block), window_lds_bytes(pass), st, b.sd, b.S,
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, w.bins, w.table, w.fine, b.K);
+    return hipGetLastError();
+}
+
+int window_blocks_per_cu(int pass, int variant, uint32_t block)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, window_fn(pass, variant), (int)block, window_lds_bytes(pass)) !=
+        hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+// Block-cooperative search over n counts: the first index whose inclusive
+// prefix sum reaches kk (1 <= kk <= total); before = the prefix sum below it.
+// Returns false if the counts total less than kk.  All threads must call it.
+__device__ bool block_find(const uint64_t* __restrict__ c, uint32_t n, uint64_t kk, uint32_t* idx, uint64_t* before,
+                           uint64_t* part /* LDS [blockDim.x + 1] */)
+{
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
+    uint64_t sum = 0;
+    for (uint32_t i = b0; i < b1; ++i) sum += c[i];
+    part[threadIdx.x + 1] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[0] = 0;
+        for (uint32_t t = 1; t <= blockDim.x; ++t) part[t] += part[t - 1];
+    }
+    __syncthreads();
+    const bool ok = part[blockDim.x] >= kk;
+    bool found = false;
+    if (ok && part[threadIdx.x] < kk && part[threadIdx.x + 1] >= kk) {
+        uint64_t run = part[threadIdx.x];
+        for (uint32_t i = b0; i < b1; ++i) {
+            if (run + c[i] >= kk) {
+                *idx = i;
+                *before = run;
+                found = true;
+                break;
+            }
+            run += c[i];
+        }
+    }
+    (void)found;
+    __syncthreads();
+    return ok;
+}
+
+// After window pass 1: per target, hit if its rank falls inside the window;
+// its fine bin and the count below that bin; pass-2 slots and table.
+__global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                                      const uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
+                                                      uint64_t* __restrict__ fine)
+{
+    __shared__ uint64_t part[257];
+    __shared__ uint32_t s_idx;
+    __shared__ uint64_t s_before;
+    __shared__ uint32_t uniq[RQA_MAX_K];
+    __shared__ uint32_t nuniq;
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    uint8_t* tb = table + (size_t)s * WIN_BINS;
+    for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) tb[i] = NO_SLOT;
+    const bool ok = w.win_ok != 0;
+    const uint64_t below = w.win_below;
+    const uint64_t* cb = bins + (size_t)s * WIN_BINS;
+    for (uint32_t r = 0; r < K; ++r) {
+        const uint64_t k = w.k[r];
+        bool hit = ok && k > below;
+        if (hit) {
+            hit = block_find(cb, WIN_BINS, k - below, &s_idx, &s_before, part);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            w.win_hit[r] = hit ? 1u : 0u;
+            if (hit) {
+                w.win_fbin[r] = s_idx;
+                w.win_base[r] = below + s_before;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uint32_t n = 0;
+        for (uint32_t r = 0; r < K; ++r)
+            if (w.win_hit[r]) uniq[n++] = w.win_fbin[r];
+        nuniq = sort_unique(uniq, n);
+    }
+    __syncthreads();
+    const uint32_t nu = nuniq;
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x)
+        w.win_slot[r] = w.win_hit[r] ? index_of(uniq, nu, w.win_fbin[r]) : (uint32_t)NO_SLOT;
+    __syncthreads();
+    for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) tb[uniq[u]] = (uint8_t)u;
+    if (threadIdx.x == 0) w.win_nslots = nu;
+    // clear the sub-bins pass 2 will count into
+    const uint32_t nsub = 1u << w.win_shift;
+    uint64_t* f = fine + (size_t)s * K * (1u << WIN_MAX_SHIFT);
+    for (uint32_t u = 0; u < nu; ++u)
+        for (uint32_t i = threadIdx.x; i < nsub; i += blockDim.x) f[(size_t)u * (1u << WIN_MAX_SHIFT) + i] = 0;
+}
+
+// After window pass 2: the sub-bin of each hit target gives its threshold;
+// count = #{key <= eps}.
+__global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                                      const uint64_t* __restrict__ fine)
+{
+    __shared__ uint64_t part[257];
+    __shared__ uint32_t s_idx;
+    __shared__ uint64_t s_before;
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    const uint32_t nsub = 1u << w.win_shift;
+    for (uint32_t r = 0; r < K; ++r) {
+        if (!w.win_hit[r]) continue;
+        const uint64_t* c = fine + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT);
+        const bool ok = block_find(c, nsub, w.k[r] - w.win_base[r], &s_idx, &s_before, part);
+        if (threadIdx.x == 0) {
+            if (ok) {
+                w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + s_idx;
+                w.count[r] = w.win_base[r] + s_before + c[s_idx];
+            } else {
+                w.win_hit[r] = 0u;
+                atomicOr(&w.status, 8u);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_window_scan(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass)
+{
+    if (pass == 1) hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.bins, w.table, w.fine);
+    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.fine);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ sketch
 
 // SplitMix64 output for counter s of stream `seed` (Steele, Lea and Flood,
@@ -1171,6 +1547,11 @@ hipError_t set_kernel_lds_limits(size_t max_dyn_lds)
     for (int v = 0; v < NUM_SELECT_VARIANTS; ++v) {
         for (int p = 1; p <= 3; ++p) {
             hipError_t e = hipFuncSetAttribute((const void*)select_fn_pass(p, v),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+            if (e != hipSuccess) err = e;
+        }
+        for (int p = 1; p <= 2; ++p) {
+            hipError_t e = hipFuncSetAttribute((const void*)window_fn(p, v),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
             if (e != hipSuccess) err = e;
         }

@@ -19,6 +19,8 @@ RQA_NORM_EUCLIDEAN = 1
 RQA_SEL_PLAIN = 0
 RQA_SEL_LEARNED = 1
 RQA_FULL_HIST = 2
+RQA_SEL_SAMPLE = 4
+RQA_SEL_WINDOW = 8
 
 STATUS = {0: "RQA_OK", -1: "RQA_ERR_INVALID_ARG", -2: "RQA_ERR_TOO_SHORT",
           -3: "RQA_ERR_NONFINITE", -4: "RQA_ERR_DEVICE", -5: "RQA_ERR_NOMEM",
@@ -61,6 +63,16 @@ SIGNATURES = {
     "rqa_autotune": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "rqa_autotune_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, ctypes.POINTER(_u32)]),
     "rqa_sketch_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _u64, _fp, ctypes.POINTER(_u32)]),
+    "rqa_mlp_init": (_i32, [_vp, _u64]),
+    "rqa_mlp_set_params": (_i32, [_vp, _fp, _u64]),
+    "rqa_mlp_get_params": (_i32, [_vp, _fp, _u64]),
+    "rqa_mlp_forward": (_i32, [_vp, _vp, _u32, _vp]),
+    "rqa_mlp_gradients": (_i32, [_vp, _vp, _vp, _u32, _fp, _dp]),
+    "rqa_mlp_train_step": (_i32, [_vp, _vp, _vp, _u32, ctypes.c_float, _dp]),
+    "rqa_mlp_set_bracket": (_i32, [_vp, _fp, _u32]),
+    "rqa_set_window": (_i32, [_vp, ctypes.c_float, ctypes.c_float]),
+    "rqa_set_sample_width": (_i32, [_vp, ctypes.c_float]),
+    "rqa_selection_stats": (_i32, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "rqa_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_tune_load": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_status_string": (ctypes.c_char_p, [_i32]),
@@ -194,6 +206,82 @@ def rqa_sketch_batch(ctx, concat, offsets, params, seed):
     _check(load().rqa_sketch_batch(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, int(seed),
                                    _p(feats, ctypes.c_float), scale.ctypes.data_as(ctypes.POINTER(_u32))))
     return feats, scale
+
+
+MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 66, 20, 27668
+
+
+def _dev_matrix(t, cols):
+    """(device pointer, rows) of a contiguous float32 CUDA tensor [rows, cols]."""
+    ptr, n = _series_ptr(t)
+    if n % cols:
+        raise ValueError(f"tensor size {n} is not a multiple of {cols}")
+    return ptr, n // cols
+
+
+def rqa_mlp_init(ctx, seed):
+    _check(load().rqa_mlp_init(ctx, int(seed)))
+
+
+def rqa_mlp_set_params(ctx, params):
+    p = _a(params, np.float32)
+    _check(load().rqa_mlp_set_params(ctx, _p(p, ctypes.c_float), p.size))
+
+
+def rqa_mlp_get_params(ctx):
+    p = np.zeros(MLP_PARAMS, np.float32)
+    _check(load().rqa_mlp_get_params(ctx, _p(p, ctypes.c_float), p.size))
+    return p
+
+
+def rqa_mlp_forward(ctx, x, y):
+    """y[B, 20] = network(x[B, 66]); x and y are CUDA float32 tensors."""
+    xp, B = _dev_matrix(x, MLP_INPUTS)
+    yp, By = _dev_matrix(y, MLP_OUTPUTS)
+    if By != B:
+        raise ValueError("x and y rows differ")
+    _check(load().rqa_mlp_forward(ctx, xp, B, yp))
+
+
+def rqa_mlp_gradients(ctx, x, t):
+    """(gradient float32[27668], loss) of the MSE on the batch."""
+    xp, B = _dev_matrix(x, MLP_INPUTS)
+    tp, Bt = _dev_matrix(t, MLP_OUTPUTS)
+    if Bt != B:
+        raise ValueError("x and t rows differ")
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float64)
+    _check(load().rqa_mlp_gradients(ctx, xp, tp, B, _p(g, ctypes.c_float), _p(loss, ctypes.c_double)))
+    return g, float(loss[0])
+
+
+def rqa_mlp_train_step(ctx, x, t, lr):
+    xp, B = _dev_matrix(x, MLP_INPUTS)
+    tp, Bt = _dev_matrix(t, MLP_OUTPUTS)
+    if Bt != B:
+        raise ValueError("x and t rows differ")
+    loss = np.zeros(1, np.float64)
+    _check(load().rqa_mlp_train_step(ctx, xp, tp, B, float(lr), _p(loss, ctypes.c_double)))
+    return float(loss[0])
+
+
+def rqa_mlp_set_bracket(ctx, delta):
+    d = _a(delta, np.float32)
+    _check(load().rqa_mlp_set_bracket(ctx, _p(d, ctypes.c_float), d.size))
+
+
+def rqa_set_window(ctx, lo, hi):
+    _check(load().rqa_set_window(ctx, float(lo), float(hi)))
+
+
+def rqa_set_sample_width(ctx, z):
+    _check(load().rqa_set_sample_width(ctx, float(z)))
+
+
+def rqa_selection_stats(ctx):
+    a, b, c = _u32(0), _u32(0), _u32(0)
+    _check(load().rqa_selection_stats(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"full_passes": a.value, "series_fallback": b.value, "targets_missed": c.value}
 
 
 def rqa_tune_save(ctx, path):
@@ -333,6 +421,36 @@ class Context:
 
     def sketch_batch(self, concat, offsets, params, seed):
         return rqa_sketch_batch(self.ctx, concat, offsets, params, seed)
+
+    def mlp_init(self, seed):
+        rqa_mlp_init(self.ctx, seed)
+
+    def mlp_set_params(self, params):
+        rqa_mlp_set_params(self.ctx, params)
+
+    def mlp_get_params(self):
+        return rqa_mlp_get_params(self.ctx)
+
+    def mlp_forward(self, x, y):
+        rqa_mlp_forward(self.ctx, x, y)
+
+    def mlp_gradients(self, x, t):
+        return rqa_mlp_gradients(self.ctx, x, t)
+
+    def mlp_train_step(self, x, t, lr):
+        return rqa_mlp_train_step(self.ctx, x, t, lr)
+
+    def mlp_set_bracket(self, delta):
+        rqa_mlp_set_bracket(self.ctx, delta)
+
+    def set_window(self, lo, hi):
+        rqa_set_window(self.ctx, lo, hi)
+
+    def set_sample_width(self, z):
+        rqa_set_sample_width(self.ctx, z)
+
+    def selection_stats(self):
+        return rqa_selection_stats(self.ctx)
 
     def tune_save(self, path):
         rqa_tune_save(self.ctx, path)

@@ -189,3 +189,143 @@ def periodic_integer(n, period, seed=0):
     rng = rng_for(100, period, n, seed)
     levels = rng.permutation(period).astype(np.float64) * 3.0 + 1.0
     return levels[np.arange(n) % period].astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Many series at once (training and evaluation sets of the threshold-bracket
+# network).  Same systems and noise model as above, iterated in float64 with
+# the state of all series of one system held in one array, so that tens of
+# thousands of series take seconds instead of hours.  Series are stored
+# back to back (concatenated) with offsets.
+
+
+def _iterate_many(lengths, transient, init, step, observe):
+    """Run `step` on the states of all series (sorted by length, longest
+    first; `step(state, a)` advances the first `a` in place) and record
+    `observe(state)` for t < length of each series."""
+    order = np.argsort(-lengths, kind="stable")
+    lens = lengths[order]
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    out = np.empty(int(offs[-1]), dtype=np.float64)
+    state = np.ascontiguousarray(init(len(lens))[..., order])   # drawn in input order
+    for _ in range(transient):
+        step(state, len(lens))
+    active = len(lens)
+    for t in range(int(lens[0]) if len(lens) else 0):
+        while active and lens[active - 1] <= t:
+            active -= 1
+        out[offs[:active] + t] = observe(state)[:active]
+        step(state, active)
+    res = [None] * len(lens)
+    for pos, idx in enumerate(order):
+        res[idx] = out[offs[pos]:offs[pos + 1]]
+    return res
+
+
+def _logistic_many(lengths, rng, r=4.0, transient=1000):
+    def step(x, a):
+        v = x[:a]
+        v *= r * (1.0 - v)
+    return _iterate_many(lengths, transient, lambda k: rng.uniform(0.1, 0.9, size=k), step, lambda x: x)
+
+
+def _lorenz_many(lengths, rng, dt=0.01, transient=5000, sigma=10.0, rho=28.0, beta=8.0 / 3.0):
+    h = dt
+
+    def f(x, y, z):
+        return sigma * (y - x), x * (rho - z) - y, x * y - beta * z
+
+    def step(s, a):
+        x, y, z = s[0, :a], s[1, :a], s[2, :a]
+        k1 = f(x, y, z)
+        k2 = f(x + 0.5 * h * k1[0], y + 0.5 * h * k1[1], z + 0.5 * h * k1[2])
+        k3 = f(x + 0.5 * h * k2[0], y + 0.5 * h * k2[1], z + 0.5 * h * k2[2])
+        k4 = f(x + h * k3[0], y + h * k3[1], z + h * k3[2])
+        x += h / 6.0 * (k1[0] + 2.0 * k2[0] + 2.0 * k3[0] + k4[0])
+        y += h / 6.0 * (k1[1] + 2.0 * k2[1] + 2.0 * k3[1] + k4[1])
+        z += h / 6.0 * (k1[2] + 2.0 * k2[2] + 2.0 * k3[2] + k4[2])
+
+    def init(k):
+        return np.array([1.0, 1.0, 1.0])[:, None] + rng.normal(0.0, 0.01, size=(3, k)).reshape(k, 3).T.copy()
+
+    res = _iterate_many(lengths, transient, init, step, lambda s: s[0])
+    return [(v - v.mean()) / v.std() for v in res]
+
+
+GROUP = 512   # series per independently seeded group of one system
+
+
+def _group(args):
+    system, si, seed, g, lengths, snrs = args
+    rng = rng_for(5, seed, si, g)
+    if system == "sine":
+        clean_ = [sine(int(n), rng) for n in lengths]
+    elif system == "logistic":
+        clean_ = _logistic_many(lengths, rng)
+    else:
+        clean_ = _lorenz_many(lengths, rng)
+    out = []
+    for c, snr in zip(clean_, snrs):
+        y = add_noise(c, snr, rng).astype(np.float32)
+        if not np.all(np.isfinite(y)) or float(np.std(y)) <= 0.0:
+            raise RuntimeError(f"degenerate synthetic series {system} group {g}")
+        out.append(y)
+    return out
+
+
+def many_series(systems, lengths, snrs, seed, workers=None):
+    """float32 series (list) for parallel lists of system names, lengths and
+    SNRs in dB.  The series of each system are cut, in input order, into
+    groups of GROUP, each generated from its own seed (seed, system, group),
+    so the result does not depend on the number of worker processes."""
+    import concurrent.futures
+    import os
+    systems = list(systems)
+    lengths = np.asarray(lengths, dtype=np.int64)
+    snrs = np.asarray(snrs, dtype=np.float64)
+    jobs, where = [], []
+    for si, system in enumerate(SYSTEMS):
+        idx = [i for i, s in enumerate(systems) if s == system]
+        for g in range(0, len(idx), GROUP):
+            part = idx[g:g + GROUP]
+            jobs.append((system, si, seed, g // GROUP, lengths[part], snrs[part]))
+            where.append(part)
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    out = [None] * len(systems)
+    if workers <= 1 or len(jobs) <= 1:
+        results = map(_group, jobs)
+    else:
+        ex = concurrent.futures.ProcessPoolExecutor(max_workers=min(workers, len(jobs)))
+        results = ex.map(_group, jobs)
+    for part, ys in zip(where, results):
+        for i, y in zip(part, ys):
+            out[i] = y
+    if workers > 1 and len(jobs) > 1:
+        ex.shutdown()
+    return out
+
+
+def bracket_set(count, seed, lo=1000, hi=100_000, snr_lo=-25.0, snr_hi=20.0, m=None):
+    """Series for training or evaluating the threshold-bracket network:
+    system uniform over the three, SNR ~ U[snr_lo, snr_hi] dB, length
+    log-uniform in [lo, hi] (lo == hi gives a fixed length), Euclidean norm,
+    w = 1, l_min = 2, K = 20 targets 0.01..0.20.  Embedding m = 3, tau = 5
+    when m == 3; m = 1 when m == 1; m=None draws 3 (tau = 5) with
+    probability 2/3 and 1 otherwise.  Returns (concat float32, offsets
+    uint64[count + 1], params list, systems, snrs)."""
+    rng = rng_for(6, seed)
+    systems = [SYSTEMS[i] for i in rng.integers(0, len(SYSTEMS), size=count)]
+    snrs = rng.uniform(snr_lo, snr_hi, size=count)
+    if lo == hi:
+        lengths = np.full(count, lo, dtype=np.int64)
+    else:
+        lengths = np.floor(10.0 ** rng.uniform(math.log10(lo), math.log10(hi), size=count)).astype(np.int64)
+    if m is None:
+        ms = np.where(rng.uniform(size=count) < 2.0 / 3.0, 3, 1)
+    else:
+        ms = np.full(count, int(m))
+    ys = many_series(systems, lengths, snrs, seed)
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint64)
+    params = [(int(mm), 5 if mm == 3 else 1, NORM_EUCLID, 1, 2) for mm in ms]
+    return np.concatenate(ys), offs, params, systems, snrs
