@@ -56,7 +56,42 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=10_000,
                     help="prefix length of the Lorenz series the oracle is timed on")
+    ap.add_argument("--tune-file", default=None,
+                    help="load launch shapes from this file if it exists, else tune and save them there")
+    ap.add_argument("--no-bracket", action="store_true", help="skip the learned-bracket evaluation")
+    ap.add_argument("--bracket-file", default=os.path.join(ROOT, "paper_2208_09136_amd", "bracket_params.npz"),
+                    help="trained bracket network (written by paper_2208_09136_amd.bracket)")
+    ap.add_argument("--bracket-series", type=int, default=200)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, one plain device copy of this many MiB (a known-size kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+def sources_digest():
+    """SHA-256 over the device sources, to tell whether stored counters still
+    describe the kernels being run."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2208_09136_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "counters_n1e5_k20.json")
+
+
+def stored_counters():
+    """Per-launch hardware counters of the timed kernels (rocprofv3 --pmc,
+    summarised in profiles/), or None when absent or taken on other sources."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return c if c.get("sources_sha256") == sources_digest() else None
 
 
 def main():
@@ -85,7 +120,13 @@ def main():
     # launch shapes from the library's autotuner (timed trials on this workload;
     # shapes never change results)
     t_tune = time.perf_counter()
-    tuned_chunk = ctx.autotune_batch(concat, offs, prm, rr)
+    if args.tune_file and os.path.exists(args.tune_file):
+        ctx.tune_load(args.tune_file)
+        tuned_chunk = None
+    else:
+        tuned_chunk = ctx.autotune_batch(concat, offs, prm, rr)
+        if args.tune_file:
+            ctx.tune_save(args.tune_file)
     t_tune = time.perf_counter() - t_tune
     ctx.set_timing(True)
 
@@ -123,6 +164,18 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
                 "algorithmic_ops_per_launch": per_launch_ops[dom], "launch_ms": ph[dom]}
+    counters = stored_counters()
+    if counters and dom in counters.get("kernels", {}):
+        kc = counters["kernels"][dom]
+        # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, each scaled by
+        # the factor a plain copy of known size gave for that counter
+        if kc.get("fetch_bytes") is not None and kc.get("write_bytes") is not None:
+            roofline["traffic"] = kc["fetch_bytes"] + kc["write_bytes"]
+            roofline["traffic_unit"] = "bytes/launch"
+        if kc.get("valu_insts") is not None:
+            # executed VALU instructions x 64 lanes against the same peak
+            roofline["valu_lane_ops_measured"] = kc["valu_insts"] * 64
+            roofline["valu_busy_frac"] = kc["valu_insts"] * 64 / (ph[dom] * 1e-3) / VALU_PEAK
 
     result = {
         "metric": METRIC, "value": value, "unit": "cell-thresholds/s", "n_gpus": 1,
@@ -143,8 +196,20 @@ def main():
     if not args.no_batch:
         result["batched"] = bench_batch(ctx, torch, rqa)
 
+    if not args.no_bracket:
+        result["learned_bracket"] = bench_bracket(ctx, torch, args)
+
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cases[0], args.cpu_sample)
+
+    if args.copy_mib > 0:
+        n = args.copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = n
 
     ctx.close()
     print(json.dumps(result), flush=True)
@@ -186,6 +251,28 @@ def bench_batch(ctx, torch, rqa, reps=3):
             "cell_thresholds_per_s": cells * K / tb, "single_calls_ms": ts * 1e3,
             "single_series_per_s": len(cases) / ts, "batched_over_single": ts / tb,
             "equal_to_single": same, "autotune_chunk_tiles": chunk, "autotune_seconds": t_tune}
+
+
+def bench_bracket(ctx, torch, args):
+    """Held-out evaluation of the threshold-bracket network: 200 series at
+    N = 5e4 (three systems, SNR ~ U[-25, 20] dB, m = 3, tau = 5, Euclidean,
+    K = 20) in one rqa_batch call with plain selection, with the network's
+    window and with the sketch-sample window; results must be identical."""
+    from paper_2208_09136_amd import bracket
+    if not os.path.exists(args.bracket_file):
+        return {"skipped": "no trained network at " + os.path.relpath(args.bracket_file, ROOT)}
+    meta = bracket.load(ctx, args.bracket_file)
+    n = 50_000
+    c, o, p, _, _ = synth.bracket_set(args.bracket_series, 13, n, n, m=3)
+    rr = np.tile(np.array(synth.RR_20), (args.bracket_series, 1))
+    ev = bracket.evaluate(ctx, torch.from_numpy(c).to("cuda:0"), o, p, rr)
+    pairs = args.bracket_series * ((n - 10 - 1) * (n - 10) // 2)
+    for name in ("plain", "network", "sample"):
+        ev[name]["cell_thresholds_per_s"] = pairs * K / ev[name]["seconds"]
+    ev["workload"] = (f"{args.bracket_series} held-out series x N={n} (sine, logistic, Lorenz-x; "
+                      "SNR U[-25,20] dB), m=3, tau=5, Euclidean, K=20; select + sweep")
+    ev["network"]["trained_on"] = meta.get("train")
+    return ev
 
 
 def cpu_baseline(case, n_sample):

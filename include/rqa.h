@@ -139,11 +139,14 @@ rqa_status rqa_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const ui
                      float *eps_out, double *rr_out, double *det_out, double *det_mean_out,
                      uint64_t *count_out);
 
-/* Per-phase device times of the last call, in milliseconds, measured with
- * HIP events on the context stream when timing is enabled (rqa_set_timing).
- * times_out[0..n_out-1] receives: [0] selection pass 1, [1] pass 2,
- * [2] pass 3, [3] sweep, [4] everything else (checks, scans, preparation).
- * Returns the number of entries written. */
+/* Per-phase device times of the last computing call (select, det curve,
+ * run, batch, sketch), in milliseconds, measured with HIP events on the
+ * context stream when timing is enabled (rqa_set_timing) and summed over
+ * all launches of the call.  times_out[0..n_out-1] receives: [0] selection
+ * pass 1, [1] pass 2, [2] pass 3, [3] sweep, [4] everything else (checks,
+ * sketch, network, scans, preparation).  Windowed selection books its two
+ * passes as passes 1 and 2; a plain fallback adds its three passes to
+ * passes 1-3.  Returns the number of entries written. */
 int rqa_phase_times(rqa_ctx *ctx, double *times_out, int n_out);
 
 /* Enable (1) or disable (0) per-phase HIP-event timing on the context. */

@@ -184,21 +184,29 @@ def evaluate(ctx, concat, offsets, params, rr, repeats=3):
     rr = np.asarray(rr, dtype=np.float64)
     out = {"series": S}
     ref = None
+    ctx.set_timing(True)
     for name, flags in (("plain", rqa.RQA_SEL_PLAIN), ("network", rqa.RQA_SEL_LEARNED),
                         ("sample", rqa.RQA_SEL_SAMPLE)):
         ctx.batch(y, offsets, params, rr, flags=flags)        # warm-up
         res, secs = _timed(lambda: ctx.batch(y, offsets, params, rr, flags=flags), repeats)
         st = ctx.selection_stats()
+        ph = ctx.phase_times()
         if ref is None:
             ref = res
         exact = all(np.array_equal(res[k], ref[k]) for k in ("eps", "count", "det", "det_mean"))
         fb = st["series_fallback"]
         out[name] = {"seconds": secs, "exact": bool(exact), "series_fallback": fb,
                      "targets_missed": st["targets_missed"],
-                     "passes_per_series": 3.0 if flags == rqa.RQA_SEL_PLAIN else 2.0 + 3.0 * fb / S}
+                     "passes_per_series": 3.0 if flags == rqa.RQA_SEL_PLAIN else 2.0 + 3.0 * fb / S,
+                     "selection_passes_ms": ph["select_pass1"] + ph["select_pass2"] + ph["select_pass3"],
+                     "sweep_ms": ph["sweep"], "other_ms": ph["other"]}
+    ctx.set_timing(False)
     for name in ("network", "sample"):
         out[name]["speedup_vs_plain"] = out["plain"]["seconds"] / out[name]["seconds"]
+        out[name]["selection_speedup_vs_plain"] = (out["plain"]["selection_passes_ms"]
+                                                   / out[name]["selection_passes_ms"])
         out[name]["miss_rate"] = out[name]["series_fallback"] / S
+        out[name]["passes_saved_per_series"] = 3.0 - out[name]["passes_per_series"]
     return out
 
 

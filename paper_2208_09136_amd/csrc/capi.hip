@@ -221,6 +221,11 @@ rqa_status ensure_host(rqa_ctx* c, size_t bytes)
     return RQA_OK;
 }
 
+void reset_phases(rqa_ctx* c)
+{
+    for (int i = 0; i < PH_N; ++i) c->phase_ms[i] = 0.0;
+}
+
 struct Timer {
     rqa_ctx* c;
     int used = 0;
@@ -239,9 +244,10 @@ struct Timer {
         ++used;
         return e;
     }
+    // adds this job's phase times to the call's totals (reset at the start
+    // of every computing entry point)
     void collect()
     {
-        for (int i = 0; i < PH_N; ++i) c->phase_ms[i] = 0.0;
         if (!c->timing) return;
         for (int i = 0; i < used; ++i) {
             float ms = 0.f;
@@ -250,7 +256,9 @@ struct Timer {
     }
 };
 
-enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3, MODE_SKETCH = 4 };
+// MODE_LINES (with MODE_SELECT): line values ride along with the keys through
+// the selection passes, giving D at the exact thresholds without a sweep.
+enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3, MODE_SKETCH = 4, MODE_LINES = 8, MODE_FUSED = 9 };
 
 struct Job {
     std::vector<Series> series;
@@ -264,6 +272,7 @@ struct Job {
     // results
     std::vector<float> eps;
     std::vector<uint64_t> kout, count_sel, count;
+    std::vector<uint64_t> dcount;    // S*K, D = #{line value <= eps} (selection with lines)
     std::vector<double> rr, det, det_mean;
     std::vector<uint64_t> M;
     std::vector<float> features;     // S*SKETCH_FEATURES (sketch mode)
@@ -306,7 +315,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         return job.M[a] > job.M[b];
     });
     // groups: consecutive device series sharing the sweep variant (and lmin for the generic one)
-    struct Group { uint32_t begin, end; int sel, swp; uint32_t nchunks; };
+    struct Group { uint32_t begin, end; int sel, swp, lsel; uint32_t nchunks; };
+    const bool lines = (job.mode & MODE_SELECT) && (job.mode & MODE_LINES);
     std::vector<Group> groups;
     uint32_t maxn = 0;
     for (uint32_t i = 0; i < S; ++i) {
@@ -314,7 +324,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const Series& z = job.series[s];
         const bool same = !groups.empty() && groups.back().swp == swp_var[s] &&
                           (swp_var[s] % 3 != 0 || job.series[order[groups.back().begin]].p.lmin == z.p.lmin);
-        if (!same) groups.push_back({i, i, sel_var[s], swp_var[s], 0});
+        if (!same)
+            groups.push_back({i, i, sel_var[s], swp_var[s], lines_variant_of(z.p.norm, z.p.m, z.p.tau, z.p.lmin), 0});
         Group& g = groups.back();
         g.end = i + 1;
         const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
@@ -358,7 +369,11 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_h2 = carve(sizeof(uint64_t) * S * K * SEL_N2);
     const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
     const bool window = (job.mode & MODE_SELECT) && job.sel != 0;
+    const size_t o_h1L = lines && !window ? carve(sizeof(uint64_t) * S * SEL_N1) : 0;
+    const size_t o_h2L = lines && !window ? carve(sizeof(uint64_t) * S * K * SEL_N2) : 0;
+    const size_t o_h3L = lines && !window ? carve(sizeof(uint64_t) * S * K * SEL_N3) : 0;
     const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
+    const size_t o_wbinsL = window && lines ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
     const size_t zero_end = off;  // tickets and histograms are cleared every call
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
@@ -368,6 +383,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_smp = window ? carve(sizeof(uint32_t) * S * SKETCH_P) : 0;
     const size_t o_wtab = window ? carve((size_t)S * WIN_BINS) : 0;
     const size_t o_wfine = window ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
+    const size_t o_wfineL = window && lines ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
     const size_t o_pred = window ? carve(sizeof(float) * S * MLP_OUT) : 0;
     const size_t o_delta = window ? carve(sizeof(float) * MLP_OUT) : 0;
     rqa_status st = ensure_pool(c, off);
@@ -380,6 +396,10 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     all.h1 = (uint64_t*)(pool + o_h1);
     all.h2 = (uint64_t*)(pool + o_h2);
     all.h3 = (uint64_t*)(pool + o_h3);
+    all.h1L = o_h1L ? (uint64_t*)(pool + o_h1L) : nullptr;
+    all.h2L = o_h2L ? (uint64_t*)(pool + o_h2L) : nullptr;
+    all.h3L = o_h3L ? (uint64_t*)(pool + o_h3L) : nullptr;
+    all.lines = lines ? 1u : 0u;
     all.T1 = (uint8_t*)(pool + o_T1);
     all.T2 = (uint8_t*)(pool + o_T2);
     all.rtab = (uint2*)(pool + o_rt);
@@ -442,6 +462,11 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         v.h1 = all.h1 + (size_t)g.begin * SEL_N1;
         v.h2 = all.h2 + (size_t)g.begin * K * SEL_N2;
         v.h3 = all.h3 + (size_t)g.begin * K * SEL_N3;
+        if (all.h1L) {
+            v.h1L = all.h1L + (size_t)g.begin * SEL_N1;
+            v.h2L = all.h2L + (size_t)g.begin * K * SEL_N2;
+            v.h3L = all.h3L + (size_t)g.begin * K * SEL_N3;
+        }
         v.T1 = all.T1 + (size_t)g.begin * SEL_N1;
         v.T2 = all.T2 + (size_t)g.begin * K * SEL_N2;
         v.rtab = all.rtab + (size_t)g.begin * RHO_TABLE;
@@ -463,6 +488,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         wb.bins = (uint64_t*)(pool + o_wbins);
         wb.table = (uint8_t*)(pool + o_wtab);
         wb.fine = (uint64_t*)(pool + o_wfine);
+        wb.binsL = lines ? (uint64_t*)(pool + o_wbinsL) : nullptr;
+        wb.fineL = lines ? (uint64_t*)(pool + o_wfineL) : nullptr;
         for (int pass = 1; pass <= 2; ++pass) {
             HIP_TRY(tm.begin(pass - 1));
             for (const Group& g : groups) {
@@ -471,13 +498,18 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                 wv.bins = wb.bins + (size_t)g.begin * WIN_BINS;
                 wv.table = wb.table + (size_t)g.begin * WIN_BINS;
                 wv.fine = wb.fine + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
+                if (lines) {
+                    wv.binsL = wb.binsL + (size_t)g.begin * WIN_BINS;
+                    wv.fineL = wb.fineL + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
+                }
+                const int var = lines ? g.lsel : g.sel;
                 const uint32_t block = 512;
-                const int per_cu = window_blocks_per_cu(pass, g.sel, block);
+                const int per_cu = window_blocks_per_cu(pass, var, block);
                 const uint32_t grid = c->grid ? c->grid
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
                 const int t = take(1);
                 if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-                HIP_TRY(launch_window_pass(sm, v, wv, pass, g.sel, grid, block, (uint32_t)t));
+                HIP_TRY(launch_window_pass(sm, v, wv, pass, var, grid, block, (uint32_t)t));
             }
             HIP_TRY(tm.end());
             HIP_TRY(tm.begin(PH_OTHER));
@@ -489,25 +521,27 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             HIP_TRY(tm.begin(pass - 1));
             for (const Group& g : groups) {
                 DevBufs v = view(g);
+                const int var = lines ? g.lsel : g.sel;
+                const bool gl = var >= NUM_SELECT_VARIANTS;  // this group counts line values
                 const uint32_t block = 512;
                 uint32_t G = 1, ngroups = 1;
                 if (pass == 2) {
                     // pass-2 slots that fit the LDS next to the 4 KB bucket table
-                    const size_t fixed = select_lds_bytes(2, K, 0);
+                    const size_t fixed = select_lds_bytes(2, K, 0, gl);
                     const size_t room = c->max_lds > fixed ? c->max_lds - fixed : 0;
-                    G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4));
+                    G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4 * (gl ? 2 : 1)));
                     if (G == 0) return fail(RQA_ERR_UNSUPPORTED, "pass 2 does not fit the LDS");
                     ngroups = (K + G - 1) / G;
-                } else if (pass == 3 && select_lds_bytes(3, K, 0) > c->max_lds) {
+                } else if (pass == 3 && select_lds_bytes(3, K, 0, gl) > c->max_lds) {
                     return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass 3", K);
                 }
-                const size_t lds = select_lds_bytes(pass, K, G);
-                const int per_cu = select_blocks_per_cu(pass, g.sel, block, lds);
+                const size_t lds = select_lds_bytes(pass, K, G, gl);
+                const int per_cu = select_blocks_per_cu(pass, var, block, lds);
                 const uint32_t grid = c->grid ? c->grid
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
                 const int t = take(ngroups);
                 if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-                HIP_TRY(launch_select_pass(sm, v, pass, g.sel, grid, block, ngroups, G, (uint32_t)t));
+                HIP_TRY(launch_select_pass(sm, v, pass, var, grid, block, ngroups, G, (uint32_t)t));
             }
             HIP_TRY(tm.end());
             HIP_TRY(tm.begin(PH_OTHER));
@@ -542,6 +576,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     job.eps.assign((size_t)S * K, 0.f);
     job.kout.assign((size_t)S * K, 0);
     job.count_sel.assign((size_t)S * K, 0);
+    if (lines) job.dcount.assign((size_t)S * K, 0);
     job.count.assign((size_t)S * K, 0);
     job.rr.assign((size_t)S * K, 0.0);
     job.det.assign((size_t)S * K, 0.0);
@@ -567,6 +602,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             job.eps[(size_t)s * K + r] = e;
             job.kout[(size_t)s * K + r] = w.k[r];
             job.count_sel[(size_t)s * K + r] = w.count[r];
+            if (lines) job.dcount[(size_t)s * K + r] = job.series[s].p.lmin <= 1 ? w.count[r] : w.dcount[r];
             if (window) job.hit[(size_t)s * K + r] = w.win_hit[r] ? 1 : 0;
         }
         if (job.mode & MODE_SWEEP) {
@@ -632,7 +668,7 @@ rqa_status single_job_setup(rqa_ctx* c, Job& job, const float* series, uint64_t 
     job.series.push_back({0, n, *p});
     job.base = series;
     job.K = K;
-    job.mode = MODE_BOTH;
+    job.mode = MODE_FUSED;
     job.k.resize(K);
     for (uint32_t r = 0; r < K; ++r)
         if ((st = target_rank(rr[r], M, &job.k[r]))) return st;
@@ -672,7 +708,7 @@ rqa_status single_job(rqa_ctx* c, Job& job, const float* series, uint64_t n, con
 rqa_status select_windowed(rqa_ctx* c, Job& job)
 {
     const uint32_t S = (uint32_t)job.series.size(), K = job.K;
-    job.mode = MODE_SELECT;
+    job.mode = MODE_SELECT | (job.mode & MODE_LINES);
     rqa_status st = run_job(c, job);
     if (st) return st;
     std::vector<uint32_t> redo;
@@ -690,7 +726,7 @@ rqa_status select_windowed(rqa_ctx* c, Job& job)
     Job plain;
     plain.base = job.base;
     plain.K = K;
-    plain.mode = MODE_SELECT;
+    plain.mode = job.mode;
     for (uint32_t s : redo) {
         plain.series.push_back(job.series[s]);
         plain.k.insert(plain.k.end(), job.k.begin() + (size_t)s * K, job.k.begin() + (size_t)(s + 1) * K);
@@ -702,37 +738,52 @@ rqa_status select_windowed(rqa_ctx* c, Job& job)
             job.eps[a] = plain.eps[b];
             job.kout[a] = plain.kout[b];
             job.count_sel[a] = plain.count_sel[b];
+            if (job.mode & MODE_LINES) job.dcount[a] = plain.dcount[b];
         }
     c->stat_passes += 3;
     return RQA_OK;
 }
 
-// Selection (plain or windowed) followed by the sweep at the selected
-// thresholds; plain selection and sweep share one job.
+// RR, DET and the averaged DET from C = #{key <= eps} and D = #{line value
+// <= eps} (Eq. 3, Eq. 4 and the averaged-determinism equation), in double.
+void finish_lines(Job& job)
+{
+    const uint32_t S = (uint32_t)job.series.size(), K = job.K;
+    job.count.assign((size_t)S * K, 0);
+    job.rr.assign((size_t)S * K, 0.0);
+    job.det.assign((size_t)S * K, 0.0);
+    job.det_mean.assign(S, 0.0);
+    for (uint32_t s = 0; s < S; ++s) {
+        double sum = 0.0;
+        for (uint32_t r = 0; r < K; ++r) {
+            const size_t i = (size_t)s * K + r;
+            const uint64_t C = job.count_sel[i], D = job.dcount[i];
+            const double det = C ? (double)D / (double)C : NAN;
+            job.count[i] = C;
+            job.rr[i] = (double)C / (double)job.M[s];
+            job.det[i] = det;
+            sum += det;
+        }
+        job.det_mean[s] = sum / (double)K;
+    }
+}
+
+// Exact thresholds (plain or windowed selection) with the line values riding
+// along, then RR and DET at them: no separate sweep.
 rqa_status select_and_sweep(rqa_ctx* c, Job& job)
 {
+    job.mode = MODE_FUSED;
+    rqa_status st;
     if (job.sel == 0) {
-        job.mode = MODE_BOTH;
         c->stat_passes = 3;
         c->stat_fallback = 0;
         c->stat_missed = 0;
-        return run_job(c, job);
+        st = run_job(c, job);
+    } else {
+        st = select_windowed(c, job);
     }
-    rqa_status st = select_windowed(c, job);
     if (st) return st;
-    Job sw;
-    sw.base = job.base;
-    sw.K = job.K;
-    sw.mode = MODE_SWEEP;
-    sw.series = job.series;
-    sw.eps_bits.resize(job.eps.size());
-    std::memcpy(sw.eps_bits.data(), job.eps.data(), sizeof(uint32_t) * job.eps.size());
-    if ((st = run_job(c, sw))) return st;
-    job.count = sw.count;
-    job.rr = sw.rr;
-    job.det = sw.det;
-    job.det_mean = sw.det_mean;
-    job.M = sw.M;
+    finish_lines(job);
     return RQA_OK;
 }
 
@@ -744,7 +795,7 @@ rqa_status build_batch_job(Job& job, uint32_t S, const float* concat, const uint
     if (S == 0 || !concat || !offsets || !p || !rr) return fail(RQA_ERR_INVALID_ARG, "S is 0 or a required pointer is NULL");
     job.base = concat;
     job.K = K;
-    job.mode = MODE_BOTH;
+    job.mode = MODE_FUSED;
     job.k.resize((size_t)S * K);
     for (uint32_t s = 0; s < S; ++s) {
         if (offsets[s + 1] < offsets[s]) return fail(RQA_ERR_INVALID_ARG, "offsets decrease at series %u", s);
@@ -958,6 +1009,7 @@ rqa_status rqa_select_thresholds(rqa_ctx* c, const float* series, uint64_t n, co
                                  const double* rr, uint32_t K, uint32_t flags, float* eps_out,
                                  uint64_t* k_out, uint64_t* count_out)
 {
+    if (c) reset_phases(c);
     int sel = 0;
     rqa_status st = check_flags_select(flags, &sel);
     if (st) return st;
@@ -986,6 +1038,7 @@ rqa_status rqa_det_curve(rqa_ctx* c, const float* series, uint64_t n, const rqa_
                          uint32_t K, uint32_t flags, uint64_t* count_out, double* rr_out, double* det_out,
                          double* det_mean_out, uint64_t* hist_out, uint64_t hist_len)
 {
+    if (c) reset_phases(c);
     if (flags & RQA_FULL_HIST || hist_out || hist_len)
         return fail(RQA_ERR_UNSUPPORTED, "the full line-length histogram is not implemented");
     if (flags) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
@@ -1006,6 +1059,7 @@ rqa_status rqa_run(rqa_ctx* c, const float* series, uint64_t n, const rqa_params
                    uint32_t flags, float* eps_out, uint64_t* k_out, uint64_t* count_out, double* rr_out,
                    double* det_out, double* det_mean_out)
 {
+    if (c) reset_phases(c);
     int sel = 0;
     rqa_status st = check_flags_select(flags, &sel);
     if (st) return st;
@@ -1029,6 +1083,7 @@ rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t
                      const double* rr, uint32_t K, uint32_t flags, float* eps_out, double* rr_out, double* det_out,
                      double* det_mean_out, uint64_t* count_out)
 {
+    if (c) reset_phases(c);
     rqa_status st = check_ctx(c);
     if (st) return st;
     int sel = 0;
@@ -1070,6 +1125,7 @@ rqa_status rqa_autotune_batch(rqa_ctx* c, uint32_t S, const float* concat, const
 rqa_status rqa_sketch_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,
                             const rqa_params* p, uint64_t seed, float* features_out, uint32_t* scale_out)
 {
+    if (c) reset_phases(c);
     rqa_status st = check_ctx(c);
     if (st) return st;
     if (S == 0 || !concat || !offsets || !p || !features_out) return fail(RQA_ERR_INVALID_ARG, "a required pointer is NULL");

@@ -41,7 +41,7 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgc
 // Per-series scalars of the tile loops (wave-uniform).
 struct SeriesScalars {
     const float* y;
-    int n, nv, m, tau, w, T, q, B, Smax, ntiles;
+    int n, nv, m, tau, w, lmin, T, q, B, Smax, ntiles;
 };
 
 __device__ __forceinline__ SeriesScalars load_scalars(const SeriesDesc& sd)
@@ -53,6 +53,7 @@ __device__ __forceinline__ SeriesScalars load_scalars(const SeriesDesc& sd)
     s.m = (int)sd.m;
     s.tau = (int)sd.tau;
     s.w = (int)sd.w;
+    s.lmin = (int)sd.lmin;
     s.T = (int)sd.T;
     s.q = (int)sd.q;
     s.B = (int)sd.B;
@@ -344,61 +345,169 @@ __device__ __forceinline__ void wave_add(unsigned long long* base, uint32_t idx,
 
 // ------------------------------------------------------------------ selection
 
-// Shared tile driver of the selection passes.  For every cell of the lane's
-// diagonal in the tile: look = body.look(key) (LDS table reads, issued for a
-// whole block of keys first), then body.count(key, look).
-template <int NORM, int MC, int TC, class Body>
+// Line value of a cell: the smallest threshold at which the cell lies on a
+// diagonal line of at least lmin recurrences (Eq. 4 and the line definition
+// after it), i.e. the minimum, over the windows of lmin consecutive cells that
+// contain it, of the window's largest key.  Cells outside the diagonal have
+// key LINE_INF and recur at no threshold.  For lmin = 2 the line value is
+// max(key_t, min(key_{t-1}, key_{t+1})).  The recurrences on lines of length
+// >= lmin at threshold eps number D(eps) = #{line value <= eps}, so the line
+// values can be histogrammed and refined next to the keys and D is known at
+// the exact threshold as soon as the threshold is.  Keys are non-negative
+// floats, so their bit patterns order like their values; LINE_INF lies above
+// every key, +inf included.
+constexpr uint32_t LINE_INF = 0xFFFFFFFFu;
+
+// Line-value classes of the counting kernels: none (keys only), lmin = 2
+// (walker path), any lmin (per-cell path with rings).
+constexpr int LV_NONE = 0, LV_2 = 1, LV_ANY = 2;
+
+// Key bit pattern of cell x on the lane's diagonal; LINE_INF outside it.
+template <int NORM, int MC, int TC>
+__device__ __forceinline__ uint32_t key_or_inf(const SeriesScalars& sd, const TileGeo& g, int x)
+{
+    const bool ok = (x >= 0) && (x < g.len);
+    const int i = ok ? x : 0;
+    const int j = ok ? x + g.d : g.d0;
+    const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, i, j, sd.m, sd.tau));
+    return ok ? u : LINE_INF;
+}
+
+// Shared tile driver of the counting passes.  For every cell of the lane's
+// diagonal in the tile: body.look(key) (LDS table reads, issued for a whole
+// block of cells first), then body.count(key, look); with line values
+// (LV != LV_NONE) also body.countL(line value, body.look(line value)).
+template <int NORM, int MC, int TC, int LV, class Body>
 __device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t tile_id, int lane, Body& body)
 {
     const TileGeo g = tile_geo(sd, tile_id, lane);
-    constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
+    constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0) && LV != LV_ANY;
     if constexpr (kFast) {
         constexpr int TW = MC == 1 ? 1 : TC;
         constexpr int HU = walk_block<NORM, MC, TW>();
         if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
             // interior: every lane's diagonal covers [t0, t1 + WALK_SLACK]
-            walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
-                uint32_t lk[HU];
+            if constexpr (LV == LV_NONE) {
+                walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    uint32_t lk[HU];
 #pragma unroll
-                for (int u = 0; u < HU; ++u) lk[u] = body.look(k[u]);
+                    for (int u = 0; u < HU; ++u) lk[u] = body.look(k[u]);
 #pragma unroll
-                for (int u = 0; u < HU; ++u)
-                    if (u < valid) body.count(k[u], lk[u]);
-            });
+                    for (int u = 0; u < HU; ++u)
+                        if (u < valid) body.count(k[u], lk[u]);
+                });
+            } else {
+                // the walk runs one cell ahead: block keys k[] are the right
+                // neighbours of the cells counted in the block
+                uint32_t um1 = key_or_inf<NORM, MC, TC>(sd, g, g.t0 - 1);
+                uint32_t u0 = key_or_inf<NORM, MC, TC>(sd, g, g.t0);
+                walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    uint32_t c[HU], v[HU], lc[HU], lv[HU];
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) {
+                        const uint32_t left = u == 0 ? um1 : (u == 1 ? u0 : k[u - 2]);
+                        c[u] = u == 0 ? u0 : k[u - 1];
+                        v[u] = max(c[u], min(left, k[u]));
+                    }
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) {
+                        lc[u] = body.look(c[u]);
+                        lv[u] = body.look(v[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < HU; ++u)
+                        if (u < valid) {
+                            body.count(c[u], lc[u]);
+                            body.countL(v[u], lv[u]);
+                        }
+                    um1 = k[HU - 2];
+                    u0 = k[HU - 1];
+                });
+            }
             return;
         }
     }
-    for (int x = g.t0; x < g.t1; ++x) {
-        if (x < g.len) {
-            const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau));
-            body.count(u, body.look(u));
+    if constexpr (LV == LV_NONE) {
+        for (int x = g.t0; x < g.t1; ++x) {
+            if (x < g.len) {
+                const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau));
+                body.count(u, body.look(u));
+            }
+        }
+    } else if constexpr (LV == LV_2) {
+        uint32_t um1 = key_or_inf<NORM, MC, TC>(sd, g, g.t0 - 1);
+        uint32_t u0 = key_or_inf<NORM, MC, TC>(sd, g, g.t0);
+        for (int x = g.t0; x < g.t1; ++x) {
+            const uint32_t up1 = key_or_inf<NORM, MC, TC>(sd, g, x + 1);
+            if (x < g.len) {
+                const uint32_t v = max(u0, min(um1, up1));
+                body.count(u0, body.look(u0));
+                body.countL(v, body.look(v));
+            }
+            um1 = u0;
+            u0 = up1;
+        }
+    } else {
+        // any lmin <= LMIN_MAX: rings of the last lmin keys and of the last
+        // lmin window maxima; the counted cell lags the newest key by h = lmin-1
+        const int h = sd.lmin - 1;
+        uint32_t rr[LMIN_MAX], ww[LMIN_MAX];
+#pragma unroll
+        for (int i = 0; i < LMIN_MAX; ++i) { rr[i] = LINE_INF; ww[i] = LINE_INF; }
+        for (int x = g.t0 - h; x < g.t1 + h; ++x) {
+            const uint32_t r = key_or_inf<NORM, MC, TC>(sd, g, x);
+#pragma unroll
+            for (int i = 0; i < LMIN_MAX - 1; ++i) rr[i] = rr[i + 1];
+            rr[LMIN_MAX - 1] = r;
+            uint32_t wmax = 0, cell = LINE_INF;
+#pragma unroll
+            for (int i = 0; i < LMIN_MAX; ++i) {
+                if (i >= LMIN_MAX - 1 - h) wmax = max(wmax, rr[i]);
+                if (i == LMIN_MAX - 1 - h) cell = rr[i];
+            }
+#pragma unroll
+            for (int i = 0; i < LMIN_MAX - 1; ++i) ww[i] = ww[i + 1];
+            ww[LMIN_MAX - 1] = wmax;
+            const int xc = x - h;
+            if (xc >= g.t0 && xc < g.len) {
+                uint32_t v = LINE_INF;
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX; ++i)
+                    if (i >= LMIN_MAX - 1 - h) v = min(v, ww[i]);
+                body.count(cell, body.look(cell));
+                body.countL(v, body.look(v));
+            }
         }
     }
 }
 
 // Bytes of a selection pass's LDS tables and bins; the work-queue word follows.
-__host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G)
+__host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G, bool lines)
 {
-    if (pass == 1) return SEL_N1 * 4;
-    if (pass == 2) return SEL_N1 + (size_t)G * SEL_N2 * 4;
+    const size_t nb = lines ? 2 : 1;
+    if (pass == 1) return nb * SEL_N1 * 4;
+    if (pass == 2) return SEL_N1 + nb * (size_t)G * SEL_N2 * 4;
     return SEL_N1 + (size_t)K * SEL_N2;
 }
 
-// Pass 1: histogram of the top SEL_B1 bits of every key.
-template <int NORM, int MC, int TC>
+// Pass 1: histogram of the top SEL_B1 bits of every key (and line value).
+template <int NORM, int MC, int TC, int LV>
 struct SelPass1 {
-    uint32_t* bins;   // LDS [SEL_N1]
+    uint32_t* bins;   // LDS [SEL_N1] (keys), then [SEL_N1] (line values)
     uint64_t* h1;     // global [S][SEL_N1]
+    uint64_t* h1L;
     bool active = true;
+    static constexpr bool L = LV != LV_NONE;
     __device__ void begin(uint32_t)
     {
-        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * SEL_N1; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
-        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * SEL_N1; i += blockDim.x) {
             const uint32_t v = bins[i];
-            if (v) atomicAdd((unsigned long long*)&h1[(size_t)s * SEL_N1 + i], (unsigned long long)v);
+            uint64_t* dst = i < SEL_N1 ? &h1[(size_t)s * SEL_N1 + i] : &h1L[(size_t)s * SEL_N1 + i - SEL_N1];
+            if (v) atomicAdd((unsigned long long*)dst, (unsigned long long)v);
         }
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
@@ -406,42 +515,51 @@ struct SelPass1 {
     {
         atomicAdd(&bins[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)], 1u);
     }
+    __device__ __forceinline__ void countL(uint32_t v, uint32_t) const
+    {
+        atomicAdd(&bins[SEL_N1 + __builtin_amdgcn_ubfe(v, SEL_SH1, SEL_B1)], 1u);
+    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
     }
 };
 
-// Pass 2: for keys whose pass-1 bucket holds a target (slot in [lo, hi)),
-// histogram the next SEL_B2 bits per slot.
-template <int NORM, int MC, int TC>
+// Pass 2: for keys (line values) whose pass-1 bucket holds a target (slot in
+// [lo, hi)), histogram the next SEL_B2 bits per slot.
+template <int NORM, int MC, int TC, int LV>
 struct SelPass2 {
     uint8_t* sT1;     // LDS [SEL_N1]
-    uint32_t* bins;   // LDS [G][SEL_N2]
+    uint32_t* bins;   // LDS [G][SEL_N2] (keys), then [G][SEL_N2] (line values)
     const uint8_t* T1;
     const SeriesWork* works;
     uint64_t* h2;     // global [S][K][SEL_N2]
+    uint64_t* h2L;
     uint32_t K, G, lo, hi;
     bool active = true;
+    static constexpr bool L = LV != LV_NONE;
     __device__ void begin(uint32_t s)
     {
         const uint32_t ns = works[s].nslots2;
         hi = min(lo + G, ns);
         active = lo < ns;
         for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
-        for (uint32_t i = threadIdx.x; i < G * SEL_N2; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * G * SEL_N2; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
         if (!active) return;
         const uint32_t n = (hi - lo) * SEL_N2;
-        uint64_t* dst = h2 + ((size_t)s * K + lo) * SEL_N2;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t v = bins[i];
-            if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
+        for (int part = 0; part < (L ? 2 : 1); ++part) {
+            uint64_t* dst = (part ? h2L : h2) + ((size_t)s * K + lo) * SEL_N2;
+            const uint32_t* src = bins + (size_t)part * G * SEL_N2;
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+                const uint32_t v = src[i];
+                if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
+            }
         }
     }
-    // slot of the key's pass-1 bucket relative to this group (>= span: none)
+    // slot of the value's pass-1 bucket relative to this group (>= span: none)
     __device__ __forceinline__ uint32_t look(uint32_t u) const
     {
         return (uint32_t)sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)] - lo;
@@ -450,15 +568,20 @@ struct SelPass2 {
     {
         if (rel < hi - lo) atomicAdd(&bins[rel * SEL_N2 + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)], 1u);
     }
+    __device__ __forceinline__ void countL(uint32_t v, uint32_t rel) const
+    {
+        if (rel < hi - lo) atomicAdd(&bins[(G + rel) * SEL_N2 + __builtin_amdgcn_ubfe(v, SEL_SH2, SEL_B2)], 1u);
+    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
     }
 };
 
-// Pass 3: for keys whose 21-bit prefix holds a target, count the last SEL_B3
-// bits per pass-3 slot directly in global memory (few keys qualify).
-template <int NORM, int MC, int TC>
+// Pass 3: for keys (line values) whose 20-bit prefix holds a target, count
+// the last SEL_B3 bits per pass-3 slot directly in global memory (few
+// qualify).
+template <int NORM, int MC, int TC, int LV>
 struct SelPass3 {
     uint8_t* sT1;     // LDS [SEL_N1]
     uint8_t* sT2;     // LDS [K][SEL_N2]
@@ -466,8 +589,10 @@ struct SelPass3 {
     const uint8_t* T2;
     const SeriesWork* works;
     uint64_t* h3;     // global [S][K][SEL_N3]
+    uint64_t* h3L;
     uint32_t K;
     unsigned long long* dst;
+    unsigned long long* dstL;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
@@ -475,9 +600,10 @@ struct SelPass3 {
         for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
         for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) sT2[i] = T2[(size_t)s * K * SEL_N2 + i];
         dst = (unsigned long long*)(h3 + (size_t)s * K * SEL_N3);
+        dstL = LV != LV_NONE ? (unsigned long long*)(h3L + (size_t)s * K * SEL_N3) : nullptr;
     }
     __device__ void flush(uint32_t) {}
-    // pass-3 slot of the key's 21-bit prefix (NO_SLOT: none)
+    // pass-3 slot of the value's 20-bit prefix (NO_SLOT: none)
     __device__ __forceinline__ uint32_t look(uint32_t u) const
     {
         const uint32_t s2 = sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
@@ -487,51 +613,62 @@ struct SelPass3 {
     {
         wave_add(dst, s3 * SEL_N3 + (u & (SEL_N3 - 1)), s3 != NO_SLOT);
     }
+    __device__ __forceinline__ void countL(uint32_t v, uint32_t s3) const
+    {
+        wave_add(dstL, s3 * SEL_N3 + (v & (SEL_N3 - 1)), s3 != NO_SLOT);
+    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
     }
 };
 
-template <int PASS, int NORM, int MC, int TC>
+template <int PASS, int NORM, int MC, int TC, int LV>
 __global__ void __launch_bounds__(1024)
 k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
          uint32_t* __restrict__ tickets, SeriesWork* __restrict__ works, const uint8_t* __restrict__ T1,
-         const uint8_t* __restrict__ T2, uint64_t* __restrict__ hist, uint32_t K, uint32_t G)
+         const uint8_t* __restrict__ T2, uint64_t* __restrict__ hist, uint64_t* __restrict__ histL, uint32_t K,
+         uint32_t G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* ticket = tickets + blockIdx.y;
-    uint32_t* slot = (uint32_t*)(smem + select_lds_bytes_dev(PASS, K, G));
+    uint32_t* slot = (uint32_t*)(smem + select_lds_bytes_dev(PASS, K, G, LV != LV_NONE));
     if constexpr (PASS == 1) {
-        SelPass1<NORM, MC, TC> body{(uint32_t*)smem, hist};
+        SelPass1<NORM, MC, TC, LV> body{(uint32_t*)smem, hist, histL};
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else if constexpr (PASS == 2) {
-        SelPass2<NORM, MC, TC> body;
+        SelPass2<NORM, MC, TC, LV> body;
         body.sT1 = (uint8_t*)smem;
         body.bins = (uint32_t*)(smem + SEL_N1);
         body.T1 = T1;
         body.works = works;
         body.h2 = hist;
+        body.h2L = histL;
         body.K = K;
         body.G = G;
         body.lo = blockIdx.y * G;
         body.hi = body.lo;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else {
-        SelPass3<NORM, MC, TC> body;
+        SelPass3<NORM, MC, TC, LV> body;
         body.sT1 = (uint8_t*)smem;
         body.sT2 = (uint8_t*)(smem + SEL_N1);
         body.T1 = T1;
         body.T2 = T2;
         body.works = works;
         body.h3 = hist;
+        body.h3L = histL;
         body.K = K;
         body.dst = nullptr;
+        body.dstL = nullptr;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     }
 }
 
-size_t select_lds_bytes(int pass, uint32_t K, uint32_t G) { return select_lds_bytes_dev(pass, K, G) + 16; }
+size_t select_lds_bytes(int pass, uint32_t K, uint32_t G, bool lines)
+{
+    return select_lds_bytes_dev(pass, K, G, lines) + 16;
+}
 
 static int mclass_of(uint32_t m, uint32_t tau)
 {
@@ -543,6 +680,13 @@ static int mclass_of(uint32_t m, uint32_t tau)
 
 int select_variant_of(uint32_t norm, uint32_t m, uint32_t tau) { return (int)norm * NUM_MCLASS + mclass_of(m, tau); }
 
+int lines_variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
+{
+    if (lmin <= 1) return select_variant_of(norm, m, tau);
+    if (lmin == 2) return LV_2 * NUM_SELECT_VARIANTS + select_variant_of(norm, m, tau);
+    return LV_ANY * NUM_SELECT_VARIANTS + (int)norm * NUM_MCLASS;
+}
+
 int variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
 {
     const int lc = (lmin == 1) ? 1 : (lmin == 2) ? 2 : 0;
@@ -550,24 +694,38 @@ int variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
 }
 
 using SelFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint8_t*,
-                       const uint8_t*, uint64_t*, uint32_t, uint32_t);
+                       const uint8_t*, uint64_t*, uint64_t*, uint32_t, uint32_t);
 
-template <int PASS, int NORM>
+template <int PASS, int NORM, int LV>
 static SelFn select_fn_n(int mclass)
 {
-    switch (mclass) {
-    case 1: return k_select<PASS, NORM, 1, 0>;
-    case 2: return k_select<PASS, NORM, 3, 3>;
-    case 3: return k_select<PASS, NORM, 3, 5>;
-    default: return k_select<PASS, NORM, 0, 0>;
+    if constexpr (LV == LV_ANY) {
+        return k_select<PASS, NORM, 0, 0, LV>;
+    } else {
+        switch (mclass) {
+        case 1: return k_select<PASS, NORM, 1, 0, LV>;
+        case 2: return k_select<PASS, NORM, 3, 3, LV>;
+        case 3: return k_select<PASS, NORM, 3, 5, LV>;
+        default: return k_select<PASS, NORM, 0, 0, LV>;
+        }
     }
+}
+
+template <int PASS, int LV>
+static SelFn select_fn_lv(int v)
+{
+    const int norm = v / NUM_MCLASS, mc = v % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? select_fn_n<PASS, RQA_NORM_MAX, LV>(mc)
+                                : select_fn_n<PASS, RQA_NORM_EUCLIDEAN, LV>(mc);
 }
 
 template <int PASS>
 static SelFn select_fn(int variant)
 {
-    const int norm = variant / NUM_MCLASS, mc = variant % NUM_MCLASS;
-    return norm == RQA_NORM_MAX ? select_fn_n<PASS, RQA_NORM_MAX>(mc) : select_fn_n<PASS, RQA_NORM_EUCLIDEAN>(mc);
+    const int lv = variant / NUM_SELECT_VARIANTS, v = variant % NUM_SELECT_VARIANTS;
+    if (lv == LV_2) return select_fn_lv<PASS, LV_2>(v);
+    if (lv == LV_ANY) return select_fn_lv<PASS, LV_ANY>(v);
+    return select_fn_lv<PASS, LV_NONE>(v);
 }
 
 static SelFn select_fn_pass(int pass, int variant)
@@ -580,10 +738,12 @@ static SelFn select_fn_pass(int pass, int variant)
 hipError_t launch_select_pass(hipStream_t st, const DevBufs& b, int pass, int variant, uint32_t grid,
                               uint32_t block, uint32_t groups, uint32_t G, uint32_t ticket_base)
 {
-    const size_t lds = select_lds_bytes(pass, b.K, G);
+    const bool lines = variant >= NUM_SELECT_VARIANTS;
+    const size_t lds = select_lds_bytes(pass, b.K, G, lines);
     uint64_t* hist = pass == 1 ? b.h1 : pass == 2 ? b.h2 : b.h3;
+    uint64_t* histL = pass == 1 ? b.h1L : pass == 2 ? b.h2L : b.h3L;
     hipLaunchKernelGGL(select_fn_pass(pass, variant), dim3(grid, groups), dim3(block), lds, st, b.sd, b.S,
-                       b.nchunks, b.chunk_tiles, b.tickets + ticket_base, b.work, b.T1, b.T2, hist, b.K, G);
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket_base, b.work, b.T1, b.T2, hist, histL, b.K, G);
     return hipGetLastError();
 }
 
@@ -662,9 +822,11 @@ __device__ __forceinline__ uint32_t index_of(const uint32_t* v, uint32_t n, uint
     return lo;
 }
 
-// After pass 1: locate each target's bucket, assign pass-2 slots, fill T1.
+// After pass 1: locate each target's bucket, assign pass-2 slots, fill T1;
+// with line values (h1L non-null) count those below each target's bucket.
 __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               uint8_t* __restrict__ T1, const uint64_t* __restrict__ h1)
+                                               uint8_t* __restrict__ T1, const uint64_t* __restrict__ h1,
+                                               const uint64_t* __restrict__ h1L)
 {
     __shared__ uint64_t cum[SEL_N1];
     __shared__ uint32_t uniq[RQA_MAX_K];
@@ -690,12 +852,21 @@ __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sd
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) t1[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.nslots2 = nu;
+    if (h1L) {
+        __syncthreads();
+        block_cumsum(h1L + (size_t)s * SEL_N1, cum, SEL_N1);
+        for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+            const uint32_t b = w.prefix[r];
+            w.belowL[r] = b ? cum[b - 1] : 0;
+        }
+    }
 }
 
 // After pass 2: resolve SEL_B2 more bits per target, assign pass-3 slots,
 // fill T2 (per pass-2 slot and sub-bucket).
 __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2)
+                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2,
+                                               const uint64_t* __restrict__ h2L)
 {
     __shared__ uint32_t uniq[RQA_MAX_K];
     __shared__ uint32_t nuniq;
@@ -716,6 +887,12 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
         }
         if (c == SEL_N2) { c = SEL_N2 - 1; atomicOr(&w.status, 2u); }
         w.below[r] += run;
+        if (h2L) {
+            const uint64_t* hl = h2L + ((size_t)s * K + w.slot[r]) * SEL_N2;
+            uint64_t runL = 0;
+            for (uint32_t i = 0; i < c; ++i) runL += hl[i];
+            w.belowL[r] += runL;
+        }
         w.prefix[r] = (w.prefix[r] << SEL_B2) | c;
         uniq[r] = w.prefix[r];
     }
@@ -734,7 +911,7 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
 
 // After pass 3: the last SEL_B3 bits give the threshold; count = #{key <= eps}.
 __global__ void __launch_bounds__(256) k_scan3(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               const uint64_t* __restrict__ h3)
+                                               const uint64_t* __restrict__ h3, const uint64_t* __restrict__ h3L)
 {
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
@@ -751,14 +928,24 @@ __global__ void __launch_bounds__(256) k_scan3(const SeriesDesc* __restrict__ sd
         if (c == SEL_N3) { c = SEL_N3 - 1; atomicOr(&w.status, 4u); }
         w.eps_bits[r] = (w.prefix[r] << SEL_B3) | c;
         w.count[r] = w.below[r] + run + h[c];
+        if (h3L) {
+            const uint64_t* hl = h3L + ((size_t)s * K + w.slot[r]) * SEL_N3;
+            uint64_t runL = 0;
+            for (uint32_t i = 0; i <= c; ++i) runL += hl[i];
+            w.dcount[r] = w.belowL[r] + runL;
+        }
     }
 }
 
 hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass)
 {
-    if (pass == 1) hipLaunchKernelGGL(k_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T1, b.h1);
-    else if (pass == 2) hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2);
-    else hipLaunchKernelGGL(k_scan3, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.h3);
+    const bool L = b.lines != 0;
+    if (pass == 1)
+        hipLaunchKernelGGL(k_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T1, b.h1, L ? b.h1L : nullptr);
+    else if (pass == 2)
+        hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2, L ? b.h2L : nullptr);
+    else
+        hipLaunchKernelGGL(k_scan3, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.h3, L ? b.h3L : nullptr);
     return hipGetLastError();
 }
 
@@ -1180,16 +1367,19 @@ hipError_t launch_window_from_sample(hipStream_t st, const DevBufs& b, const uin
     return hipGetLastError();
 }
 
-// Window pass 1: count keys below the window and histogram the window in
-// WIN_BINS fine bins.
-template <int NORM, int MC, int TC>
+// Window pass 1: count keys (and line values) below the window and
+// histogram the window in WIN_BINS fine bins.
+template <int NORM, int MC, int TC, int LV>
 struct WinPass1 {
-    uint32_t* bins;       // LDS [WIN_BINS]
+    uint32_t* bins;       // LDS [WIN_BINS] keys, then [WIN_BINS] line values
     uint64_t* gbins;      // global [S][WIN_BINS]
+    uint64_t* gbinsL;
     SeriesWork* works;
     uint32_t lo, span, shift;
     uint32_t below = 0;   // per lane
+    uint32_t belowL = 0;
     bool active = true;
+    static constexpr bool L = LV != LV_NONE;
     __device__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
@@ -1198,17 +1388,21 @@ struct WinPass1 {
         shift = uniform(w.win_shift);
         active = uniform(w.win_ok) != 0;
         below = 0;
-        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) bins[i] = 0u;
+        belowL = 0;
+        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * WIN_BINS; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
         if (!active) return;
-        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * WIN_BINS; i += blockDim.x) {
             const uint32_t v = bins[i];
-            if (v) atomicAdd((unsigned long long*)&gbins[(size_t)s * WIN_BINS + i], (unsigned long long)v);
+            uint64_t* dst = i < WIN_BINS ? &gbins[(size_t)s * WIN_BINS + i] : &gbinsL[(size_t)s * WIN_BINS + i - WIN_BINS];
+            if (v) atomicAdd((unsigned long long*)dst, (unsigned long long)v);
         }
         if (below) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)below);
+        if (belowL) atomicAdd((unsigned long long*)&works[s].win_belowL, (unsigned long long)belowL);
         below = 0;
+        belowL = 0;
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
     __device__ __forceinline__ void count(uint32_t u, uint32_t)
@@ -1217,23 +1411,31 @@ struct WinPass1 {
         below += u < lo ? 1u : 0u;
         if (rel <= span) atomicAdd(&bins[rel >> shift], 1u);
     }
+    __device__ __forceinline__ void countL(uint32_t v, uint32_t)
+    {
+        const uint32_t rel = v - lo;
+        belowL += v < lo ? 1u : 0u;
+        if (rel <= span) atomicAdd(&bins[WIN_BINS + (rel >> shift)], 1u);
+    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
     }
 };
 
-// Window pass 2: keys in a target's fine bin add to that bin's 2^shift
-// sub-bins in global memory (few keys qualify).
-template <int NORM, int MC, int TC>
+// Window pass 2: keys (line values) in a target's fine bin add to that bin's
+// 2^shift sub-bins in global memory (few qualify).
+template <int NORM, int MC, int TC, int LV>
 struct WinPass2 {
     uint8_t* table;       // LDS [WIN_BINS] fine bin -> slot
     const uint8_t* gtable;
     uint64_t* fine;       // global [S][K][1 << WIN_MAX_SHIFT]
+    uint64_t* fineL;
     SeriesWork* works;
     uint32_t K;
     uint32_t lo, span, shift;
     unsigned long long* dst;
+    unsigned long long* dstL;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
@@ -1244,6 +1446,7 @@ struct WinPass2 {
         active = uniform(w.win_ok) != 0 && uniform(w.win_nslots) != 0;
         for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) table[i] = gtable[(size_t)s * WIN_BINS + i];
         dst = (unsigned long long*)(fine + (size_t)s * K * (1u << WIN_MAX_SHIFT));
+        dstL = LV != LV_NONE ? (unsigned long long*)(fineL + (size_t)s * K * (1u << WIN_MAX_SHIFT)) : nullptr;
     }
     __device__ void flush(uint32_t) {}
     __device__ __forceinline__ uint32_t look(uint32_t u) const
@@ -1258,79 +1461,121 @@ struct WinPass2 {
         const uint32_t sub = (u - lo) & ((1u << shift) - 1u);
         wave_add(dst, sl * (1u << WIN_MAX_SHIFT) + sub, sl != NO_SLOT);
     }
+    __device__ __forceinline__ void countL(uint32_t v, uint32_t sl) const
+    {
+        const uint32_t sub = (v - lo) & ((1u << shift) - 1u);
+        wave_add(dstL, sl * (1u << WIN_MAX_SHIFT) + sub, sl != NO_SLOT);
+    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
     }
 };
 
-__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass) { return (pass == 1 ? WIN_BINS * 4 : WIN_BINS) + 16; }
+__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass, bool lines)
+{
+    return (pass == 1 ? (lines ? 2 : 1) * WIN_BINS * 4 : WIN_BINS) + 16;
+}
 
-size_t window_lds_bytes(int pass) { return window_lds_bytes_dev(pass); }
+size_t window_lds_bytes(int pass, bool lines) { return window_lds_bytes_dev(pass, lines); }
 
-template <int PASS, int NORM, int MC, int TC>
+template <int PASS, int NORM, int MC, int TC, int LV>
 __global__ void __launch_bounds__(1024)
 k_window(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
-         uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, uint64_t* __restrict__ bins,
-         const uint8_t* __restrict__ table, uint64_t* __restrict__ fine, uint32_t K)
+         uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, WinBufs wb, uint32_t K)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* slot = (uint32_t*)(smem + window_lds_bytes_dev(PASS) - 16);
+    uint32_t* slot = (uint32_t*)(smem + window_lds_bytes_dev(PASS, LV != LV_NONE) - 16);
     if constexpr (PASS == 1) {
-        WinPass1<NORM, MC, TC> body;
+        WinPass1<NORM, MC, TC, LV> body;
         body.bins = (uint32_t*)smem;
-        body.gbins = bins;
+        body.gbins = wb.bins;
+        body.gbinsL = wb.binsL;
         body.works = works;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else {
-        WinPass2<NORM, MC, TC> body;
+        WinPass2<NORM, MC, TC, LV> body;
         body.table = (uint8_t*)smem;
-        body.gtable = table;
-        body.fine = fine;
+        body.gtable = wb.table;
+        body.fine = wb.fine;
+        body.fineL = wb.fineL;
         body.works = works;
         body.K = K;
         body.dst = nullptr;
+        body.dstL = nullptr;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     }
 }
 
-using WinFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, uint64_t*,
-                       const uint8_t*, uint64_t*, uint32_t);
+using WinFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, WinBufs, uint32_t);
 
-template <int PASS, int NORM>
+template <int PASS, int NORM, int LV>
 static WinFn window_fn_n(int mclass)
 {
-    switch (mclass) {
-    case 1: return k_window<PASS, NORM, 1, 0>;
-    case 2: return k_window<PASS, NORM, 3, 3>;
-    case 3: return k_window<PASS, NORM, 3, 5>;
-    default: return k_window<PASS, NORM, 0, 0>;
+    if constexpr (LV == LV_ANY) {
+        return k_window<PASS, NORM, 0, 0, LV>;
+    } else {
+        switch (mclass) {
+        case 1: return k_window<PASS, NORM, 1, 0, LV>;
+        case 2: return k_window<PASS, NORM, 3, 3, LV>;
+        case 3: return k_window<PASS, NORM, 3, 5, LV>;
+        default: return k_window<PASS, NORM, 0, 0, LV>;
+        }
     }
 }
 
-static WinFn window_fn(int pass, int variant)
+template <int PASS, int LV>
+static WinFn window_fn_lv(int v)
 {
-    const int norm = variant / NUM_MCLASS, mc = variant % NUM_MCLASS;
-    if (pass == 1)
-        return norm == RQA_NORM_MAX ? window_fn_n<1, RQA_NORM_MAX>(mc) : window_fn_n<1, RQA_NORM_EUCLIDEAN>(mc);
-    return norm == RQA_NORM_MAX ? window_fn_n<2, RQA_NORM_MAX>(mc) : window_fn_n<2, RQA_NORM_EUCLIDEAN>(mc);
+    const int norm = v / NUM_MCLASS, mc = v % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? window_fn_n<PASS, RQA_NORM_MAX, LV>(mc) : window_fn_n<PASS, RQA_NORM_EUCLIDEAN, LV>(mc);
 }
+
+template <int PASS>
+static WinFn window_fn_p(int variant)
+{
+    const int lv = variant / NUM_SELECT_VARIANTS, v = variant % NUM_SELECT_VARIANTS;
+    if (lv == LV_2) return window_fn_lv<PASS, LV_2>(v);
+    if (lv == LV_ANY) return window_fn_lv<PASS, LV_ANY>(v);
+    return window_fn_lv<PASS, LV_NONE>(v);
+}
+
+static WinFn window_fn(int pass, int variant) { return pass == 1 ? window_fn_p<1>(variant) : window_fn_p<2>(variant); }
 
 hipError_t launch_window_pass(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass, int variant, uint32_t grid,
                               uint32_t block, uint32_t ticket)
 {
-    hipLaunchKernelGGL(window_fn(pass, variant), dim3(grid), dim3(block), window_lds_bytes(pass), st, b.sd, b.S,
-                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, w.bins, w.table, w.fine, b.K);
+    const bool lines = variant >= NUM_SELECT_VARIANTS;
+    hipLaunchKernelGGL(window_fn(pass, variant), dim3(grid), dim3(block), window_lds_bytes(pass, lines), st, b.sd,
+                       b.S, b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, w, b.K);
     return hipGetLastError();
 }
 
 int window_blocks_per_cu(int pass, int variant, uint32_t block)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, window_fn(pass, variant), (int)block, window_lds_bytes(pass)) !=
-        hipSuccess)
+    const bool lines = variant >= NUM_SELECT_VARIANTS;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, window_fn(pass, variant), (int)block,
+                                                     window_lds_bytes(pass, lines)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
+}
+
+// Sum of c[0..n) over the block; every thread gets it.  part: LDS
+// [blockDim.x], blockDim.x a power of two.  All threads must call it.
+__device__ uint64_t block_sum(const uint64_t* __restrict__ c, uint32_t n, uint64_t* part)
+{
+    uint64_t v = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += c[i];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    const uint64_t r = part[0];
+    __syncthreads();
+    return r;
 }
 
 // Block-cooperative search over n counts: the first index whose inclusive
@@ -1372,9 +1617,11 @@ __device__ bool block_find(const uint64_t* __restrict__ c, uint32_t n, uint64_t 
 // After window pass 1: per target, hit if its rank falls inside the window;
 // its fine bin and the count below that bin; pass-2 slots and table.
 __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                                      const uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
-                                                      uint64_t* __restrict__ fine)
+                                                      WinBufs wb, uint32_t lines)
 {
+    const uint64_t* __restrict__ bins = wb.bins;
+    uint8_t* __restrict__ table = wb.table;
+    uint64_t* __restrict__ fine = wb.fine;
     __shared__ uint64_t part[257];
     __shared__ uint32_t s_idx;
     __shared__ uint64_t s_before;
@@ -1417,18 +1664,31 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
     __syncthreads();
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) tb[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.win_nslots = nu;
+    // line values below each hit target's fine bin
+    if (lines) {
+        const uint64_t* cl = wb.binsL + (size_t)s * WIN_BINS;
+        const uint64_t belowL = w.win_belowL;
+        for (uint32_t r = 0; r < K; ++r) {
+            if (!w.win_hit[r]) continue;
+            const uint64_t v = block_sum(cl, w.win_fbin[r], part);
+            if (threadIdx.x == 0) w.win_baseL[r] = belowL + v;
+        }
+    }
     // clear the sub-bins pass 2 will count into
     const uint32_t nsub = 1u << w.win_shift;
-    uint64_t* f = fine + (size_t)s * K * (1u << WIN_MAX_SHIFT);
-    for (uint32_t u = 0; u < nu; ++u)
-        for (uint32_t i = threadIdx.x; i < nsub; i += blockDim.x) f[(size_t)u * (1u << WIN_MAX_SHIFT) + i] = 0;
+    for (int part_ = 0; part_ < (lines ? 2 : 1); ++part_) {
+        uint64_t* f = (part_ ? wb.fineL : fine) + (size_t)s * K * (1u << WIN_MAX_SHIFT);
+        for (uint32_t u = 0; u < nu; ++u)
+            for (uint32_t i = threadIdx.x; i < nsub; i += blockDim.x) f[(size_t)u * (1u << WIN_MAX_SHIFT) + i] = 0;
+    }
 }
 
 // After window pass 2: the sub-bin of each hit target gives its threshold;
 // count = #{key <= eps}.
 __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                                      const uint64_t* __restrict__ fine)
+                                                      WinBufs wb, uint32_t lines)
 {
+    const uint64_t* __restrict__ fine = wb.fine;
     __shared__ uint64_t part[257];
     __shared__ uint32_t s_idx;
     __shared__ uint64_t s_before;
@@ -1440,10 +1700,14 @@ __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restri
         if (!w.win_hit[r]) continue;
         const uint64_t* c = fine + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT);
         const bool ok = block_find(c, nsub, w.k[r] - w.win_base[r], &s_idx, &s_before, part);
+        uint64_t inL = 0;
+        if (ok && lines)
+            inL = block_sum(wb.fineL + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT), s_idx + 1, part);
         if (threadIdx.x == 0) {
             if (ok) {
                 w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + s_idx;
                 w.count[r] = w.win_base[r] + s_before + c[s_idx];
+                if (lines) w.dcount[r] = w.win_baseL[r] + inL;
             } else {
                 w.win_hit[r] = 0u;
                 atomicOr(&w.status, 8u);
@@ -1455,8 +1719,8 @@ __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restri
 
 hipError_t launch_window_scan(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass)
 {
-    if (pass == 1) hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.bins, w.table, w.fine);
-    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.fine);
+    if (pass == 1) hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w, b.lines);
+    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w, b.lines);
     return hipGetLastError();
 }
 
@@ -1544,17 +1808,23 @@ hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint
 hipError_t set_kernel_lds_limits(size_t max_dyn_lds)
 {
     hipError_t err = hipSuccess;
+    // selection and window kernels: plain, lmin = 2 and any-lmin line classes
+    for (int lv = 0; lv < 3; ++lv) {
+        for (int v0 = 0; v0 < NUM_SELECT_VARIANTS; ++v0) {
+            const int v = lv * NUM_SELECT_VARIANTS + v0;
+            for (int p = 1; p <= 3; ++p) {
+                hipError_t e = hipFuncSetAttribute((const void*)select_fn_pass(p, v),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+                if (e != hipSuccess) err = e;
+            }
+            for (int p = 1; p <= 2; ++p) {
+                hipError_t e = hipFuncSetAttribute((const void*)window_fn(p, v),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+                if (e != hipSuccess) err = e;
+            }
+        }
+    }
     for (int v = 0; v < NUM_SELECT_VARIANTS; ++v) {
-        for (int p = 1; p <= 3; ++p) {
-            hipError_t e = hipFuncSetAttribute((const void*)select_fn_pass(p, v),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
-            if (e != hipSuccess) err = e;
-        }
-        for (int p = 1; p <= 2; ++p) {
-            hipError_t e = hipFuncSetAttribute((const void*)window_fn(p, v),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
-            if (e != hipSuccess) err = e;
-        }
         for (int l = 0; l < 3; ++l) {
             hipError_t e = hipFuncSetAttribute((const void*)sweep_fn(v * 3 + l),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);

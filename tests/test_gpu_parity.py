@@ -329,3 +329,21 @@ def test_sketch_matches_oracle(ctx):
         f, sc = sketch.sketch(c["y"], c["m"], c["tau"], c["norm"], c["theiler"], seed=777 + s)
         assert int(scale[s]) == sc
         assert np.array_equal(feats[s], f)
+
+
+@pytest.mark.parametrize("m,tau,norm,w,lmin", [
+    (1, 1, 0, 1, 2), (3, 5, 1, 1, 2), (3, 3, 0, 2, 2), (2, 3, 1, 1, 2), (3, 5, 1, 1, 3),
+    (1, 1, 1, 1, 7), (3, 5, 0, 5, 16), (1, 1, 0, 1, 1)])
+def test_selection_lines_equal_sweep(ctx, m, tau, norm, w, lmin):
+    # D counted by line values inside the radix selection equals D from the
+    # separate line sweep at the same thresholds (two independent device
+    # algorithms), on a series long enough for interior walker tiles
+    y = synth.series("logistic", 5000, 0.0, (9, m, tau, lmin))
+    p = (m, tau, norm, w, lmin)
+    rr = np.array([0.001, 0.01, 0.02, 0.05, 0.1, 0.13, 0.2, 0.35])
+    print(f"[lines] m={m} tau={tau} norm={norm} w={w} lmin={lmin}", flush=True)
+    got = ctx.run(dev(y), p, rr)
+    dc = ctx.det_curve(dev(y), p, got["eps"])
+    assert np.array_equal(dc["count"], got["count"])
+    assert np.array_equal(dc["det"], got["det"], equal_nan=True)
+    assert dc["det_mean"] == got["det_mean"] or (np.isnan(dc["det_mean"]) and np.isnan(got["det_mean"]))

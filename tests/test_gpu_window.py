@@ -102,3 +102,26 @@ def test_batch_sample_window_equals_plain(ctx):
     got = ctx.batch(concat, offs, [prm(c) for c in cases], rr, flags=SAMPLE)
     for key in ("eps", "count", "det", "det_mean"):
         assert np.array_equal(got[key], plain[key]), key
+
+
+@pytest.mark.parametrize("lmin", [1, 2, 3, 6])
+@pytest.mark.parametrize("m,tau,norm", [(1, 1, 0), (3, 5, 1), (2, 3, 1)])
+def test_window_lines_match_plain_and_sweep(ctx, lmin, m, tau, norm):
+    # line values refined inside the window give the same D as the plain
+    # three-pass refinement and as the separate sweep at the same thresholds
+    y = synth.series("lorenz", 2500, 3.0, (8, m, tau, lmin))
+    p = (m, tau, norm, 1, lmin)
+    rr = np.array(synth.RR_20)
+    print(f"[window-lines] m={m} tau={tau} norm={norm} lmin={lmin}", flush=True)
+    plain = ctx.run(dev(y), p, rr)
+    for flags in (SAMPLE, WINDOW):
+        if flags == WINDOW:
+            ctx.set_window(float(plain["eps"].min()) * 0.9, float(plain["eps"].max()) * 1.1)
+        got = ctx.run(dev(y), p, rr, flags=flags)
+        st = ctx.selection_stats()
+        for key in ("eps", "count", "det", "det_mean"):
+            assert np.array_equal(got[key], plain[key]), (flags, key)
+        if flags == WINDOW:
+            assert st["series_fallback"] == 0 and st["full_passes"] == 2
+    dc = ctx.det_curve(dev(y), p, plain["eps"])
+    assert np.array_equal(dc["count"], plain["count"]) and np.array_equal(dc["det"], plain["det"])
