@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true", help="skip the 600-series ensemble")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=10_000,
+    ap.add_argument("--cpu-sample", type=int, default=15_000,
                     help="prefix length of the Lorenz series the oracle is timed on")
     ap.add_argument("--tune-file", default=None,
                     help="load launch shapes from this file if it exists, else tune and save them there")

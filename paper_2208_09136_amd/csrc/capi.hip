@@ -256,8 +256,9 @@ struct Timer {
     }
 };
 
-// MODE_LINES (with MODE_SELECT): line values ride along with the keys through
-// the selection passes, giving D at the exact thresholds without a sweep.
+// MODE_FUSED: counting passes, then the range sweep, which resolves the
+// last bits of every threshold and counts C and D at it in one pass.
+// MODE_BOTH: three counting passes, then the sweep at the thresholds found.
 enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3, MODE_SKETCH = 4, MODE_LINES = 8, MODE_FUSED = 9 };
 
 struct Job {
@@ -272,7 +273,7 @@ struct Job {
     // results
     std::vector<float> eps;
     std::vector<uint64_t> kout, count_sel, count;
-    std::vector<uint64_t> dcount;    // S*K, D = #{line value <= eps} (selection with lines)
+    std::vector<uint64_t> dcount;    // S*K, D (fused mode)
     std::vector<double> rr, det, det_mean;
     std::vector<uint64_t> M;
     std::vector<float> features;     // S*SKETCH_FEATURES (sketch mode)
@@ -315,8 +316,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         return job.M[a] > job.M[b];
     });
     // groups: consecutive device series sharing the sweep variant (and lmin for the generic one)
-    struct Group { uint32_t begin, end; int sel, swp, lsel; uint32_t nchunks; };
-    const bool lines = (job.mode & MODE_SELECT) && (job.mode & MODE_LINES);
+    struct Group { uint32_t begin, end; int sel, swp; uint32_t nchunks; };
+    const bool fused = (job.mode & MODE_SELECT) && (job.mode & MODE_LINES);
     std::vector<Group> groups;
     uint32_t maxn = 0;
     for (uint32_t i = 0; i < S; ++i) {
@@ -324,8 +325,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const Series& z = job.series[s];
         const bool same = !groups.empty() && groups.back().swp == swp_var[s] &&
                           (swp_var[s] % 3 != 0 || job.series[order[groups.back().begin]].p.lmin == z.p.lmin);
-        if (!same)
-            groups.push_back({i, i, sel_var[s], swp_var[s], lines_variant_of(z.p.norm, z.p.m, z.p.tau, z.p.lmin), 0});
+        if (!same) groups.push_back({i, i, sel_var[s], swp_var[s], 0});
         Group& g = groups.back();
         g.end = i + 1;
         const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
@@ -369,11 +369,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_h2 = carve(sizeof(uint64_t) * S * K * SEL_N2);
     const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
     const bool window = (job.mode & MODE_SELECT) && job.sel != 0;
-    const size_t o_h1L = lines && !window ? carve(sizeof(uint64_t) * S * SEL_N1) : 0;
-    const size_t o_h2L = lines && !window ? carve(sizeof(uint64_t) * S * K * SEL_N2) : 0;
-    const size_t o_h3L = lines && !window ? carve(sizeof(uint64_t) * S * K * SEL_N3) : 0;
     const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
-    const size_t o_wbinsL = window && lines ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
     const size_t zero_end = off;  // tickets and histograms are cleared every call
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
@@ -382,8 +378,11 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_feat = sketch ? carve(sizeof(float) * S * SKETCH_FEATURES) : 0;
     const size_t o_smp = window ? carve(sizeof(uint32_t) * S * SKETCH_P) : 0;
     const size_t o_wtab = window ? carve((size_t)S * WIN_BINS) : 0;
-    const size_t o_wfine = window ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
-    const size_t o_wfineL = window && lines ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
+    const size_t o_wfine = window && !fused ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
+    // range sweep: fine counters of keys and line values, cleared by the set-up kernel
+    const uint32_t fine_stride = fused ? K << (window ? WIN_MAX_SHIFT : (uint32_t)SEL_B3) : 0;
+    const size_t o_fineK = fused ? carve(sizeof(uint64_t) * S * fine_stride) : 0;
+    const size_t o_fineL = fused ? carve(sizeof(uint64_t) * S * fine_stride) : 0;
     const size_t o_pred = window ? carve(sizeof(float) * S * MLP_OUT) : 0;
     const size_t o_delta = window ? carve(sizeof(float) * MLP_OUT) : 0;
     rqa_status st = ensure_pool(c, off);
@@ -396,10 +395,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     all.h1 = (uint64_t*)(pool + o_h1);
     all.h2 = (uint64_t*)(pool + o_h2);
     all.h3 = (uint64_t*)(pool + o_h3);
-    all.h1L = o_h1L ? (uint64_t*)(pool + o_h1L) : nullptr;
-    all.h2L = o_h2L ? (uint64_t*)(pool + o_h2L) : nullptr;
-    all.h3L = o_h3L ? (uint64_t*)(pool + o_h3L) : nullptr;
-    all.lines = lines ? 1u : 0u;
+    all.fineK = fused ? (uint64_t*)(pool + o_fineK) : nullptr;
+    all.fineL = fused ? (uint64_t*)(pool + o_fineL) : nullptr;
+    all.fine_stride = fine_stride;
     all.T1 = (uint8_t*)(pool + o_T1);
     all.T2 = (uint8_t*)(pool + o_T2);
     all.rtab = (uint2*)(pool + o_rt);
@@ -462,10 +460,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         v.h1 = all.h1 + (size_t)g.begin * SEL_N1;
         v.h2 = all.h2 + (size_t)g.begin * K * SEL_N2;
         v.h3 = all.h3 + (size_t)g.begin * K * SEL_N3;
-        if (all.h1L) {
-            v.h1L = all.h1L + (size_t)g.begin * SEL_N1;
-            v.h2L = all.h2L + (size_t)g.begin * K * SEL_N2;
-            v.h3L = all.h3L + (size_t)g.begin * K * SEL_N3;
+        if (fused) {
+            v.fineK = all.fineK + (size_t)g.begin * fine_stride;
+            v.fineL = all.fineL + (size_t)g.begin * fine_stride;
         }
         v.T1 = all.T1 + (size_t)g.begin * SEL_N1;
         v.T2 = all.T2 + (size_t)g.begin * K * SEL_N2;
@@ -487,22 +484,17 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         WinBufs wb;
         wb.bins = (uint64_t*)(pool + o_wbins);
         wb.table = (uint8_t*)(pool + o_wtab);
-        wb.fine = (uint64_t*)(pool + o_wfine);
-        wb.binsL = lines ? (uint64_t*)(pool + o_wbinsL) : nullptr;
-        wb.fineL = lines ? (uint64_t*)(pool + o_wfineL) : nullptr;
-        for (int pass = 1; pass <= 2; ++pass) {
+        wb.fine = fused ? nullptr : (uint64_t*)(pool + o_wfine);
+        // fused: window pass 1 only; the range sweep resolves the fine bins
+        for (int pass = 1; pass <= (fused ? 1 : 2); ++pass) {
             HIP_TRY(tm.begin(pass - 1));
             for (const Group& g : groups) {
                 DevBufs v = view(g);
                 WinBufs wv = wb;
                 wv.bins = wb.bins + (size_t)g.begin * WIN_BINS;
                 wv.table = wb.table + (size_t)g.begin * WIN_BINS;
-                wv.fine = wb.fine + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
-                if (lines) {
-                    wv.binsL = wb.binsL + (size_t)g.begin * WIN_BINS;
-                    wv.fineL = wb.fineL + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
-                }
-                const int var = lines ? g.lsel : g.sel;
+                wv.fine = fused ? nullptr : wb.fine + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
+                const int var = g.sel;
                 const uint32_t block = 512;
                 const int per_cu = window_blocks_per_cu(pass, var, block);
                 const uint32_t grid = c->grid ? c->grid
@@ -517,25 +509,25 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             HIP_TRY(tm.end());
         }
     } else if (job.mode & MODE_SELECT) {
-        for (int pass = 1; pass <= 3; ++pass) {
+        // fused: passes 1 and 2; the range sweep takes the place of pass 3
+        for (int pass = 1; pass <= (fused ? 2 : 3); ++pass) {
             HIP_TRY(tm.begin(pass - 1));
             for (const Group& g : groups) {
                 DevBufs v = view(g);
-                const int var = lines ? g.lsel : g.sel;
-                const bool gl = var >= NUM_SELECT_VARIANTS;  // this group counts line values
+                const int var = g.sel;
                 const uint32_t block = 512;
                 uint32_t G = 1, ngroups = 1;
                 if (pass == 2) {
-                    // pass-2 slots that fit the LDS next to the 4 KB bucket table
-                    const size_t fixed = select_lds_bytes(2, K, 0, gl);
+                    // pass-2 slots that fit the LDS next to the bucket table
+                    const size_t fixed = select_lds_bytes(2, K, 0);
                     const size_t room = c->max_lds > fixed ? c->max_lds - fixed : 0;
-                    G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4 * (gl ? 2 : 1)));
+                    G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4));
                     if (G == 0) return fail(RQA_ERR_UNSUPPORTED, "pass 2 does not fit the LDS");
                     ngroups = (K + G - 1) / G;
-                } else if (pass == 3 && select_lds_bytes(3, K, 0, gl) > c->max_lds) {
+                } else if (pass == 3 && select_lds_bytes(3, K, 0) > c->max_lds) {
                     return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass 3", K);
                 }
-                const size_t lds = select_lds_bytes(pass, K, G, gl);
+                const size_t lds = select_lds_bytes(pass, K, G);
                 const int per_cu = select_blocks_per_cu(pass, var, block, lds);
                 const uint32_t grid = c->grid ? c->grid
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
@@ -549,23 +541,29 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             HIP_TRY(tm.end());
         }
     }
-    if (job.mode & MODE_SWEEP) {
+    if ((job.mode & MODE_SWEEP) || fused) {
         HIP_TRY(tm.begin(PH_OTHER));
-        HIP_TRY(launch_sweep_prep(sm, all));
+        if (fused) HIP_TRY(launch_range_prep(sm, all, window));
+        else HIP_TRY(launch_sweep_prep(sm, all));
         HIP_TRY(tm.end());
         HIP_TRY(tm.begin(PH_SWEEP));
         for (const Group& g : groups) {
             DevBufs v = view(g);
             const uint32_t block = 512;
-            const size_t lds = sweep_lds_bytes(K);
-            const int per_cu = sweep_blocks_per_cu(g.swp, block, lds);
+            const size_t lds = sweep_lds_bytes(fused ? 2 * K + 1 : K, fused);
+            const int per_cu = sweep_blocks_per_cu(g.swp, fused, block, lds);
             const uint32_t grid = c->grid ? c->grid
                                           : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
             const int t = take(1);
             if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-            HIP_TRY(launch_sweep(sm, v, g.swp, grid, block, (uint32_t)t));
+            HIP_TRY(launch_sweep(sm, v, g.swp, fused, grid, block, (uint32_t)t));
         }
         HIP_TRY(tm.end());
+        if (fused) {
+            HIP_TRY(tm.begin(PH_OTHER));
+            HIP_TRY(launch_range_scan(sm, all));
+            HIP_TRY(tm.end());
+        }
     }
     HIP_TRY(hipMemcpyAsync(h_out, all.work, hs_work, hipMemcpyDeviceToHost, sm));
     if (hs_feat) HIP_TRY(hipMemcpyAsync(h_feat, pool + o_feat, hs_feat, hipMemcpyDeviceToHost, sm));
@@ -576,7 +574,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     job.eps.assign((size_t)S * K, 0.f);
     job.kout.assign((size_t)S * K, 0);
     job.count_sel.assign((size_t)S * K, 0);
-    if (lines) job.dcount.assign((size_t)S * K, 0);
+    if (fused) job.dcount.assign((size_t)S * K, 0);
     job.count.assign((size_t)S * K, 0);
     job.rr.assign((size_t)S * K, 0.0);
     job.det.assign((size_t)S * K, 0.0);
@@ -602,8 +600,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             job.eps[(size_t)s * K + r] = e;
             job.kout[(size_t)s * K + r] = w.k[r];
             job.count_sel[(size_t)s * K + r] = w.count[r];
-            if (lines) job.dcount[(size_t)s * K + r] = job.series[s].p.lmin <= 1 ? w.count[r] : w.dcount[r];
-            if (window) job.hit[(size_t)s * K + r] = w.win_hit[r] ? 1 : 0;
+            if (fused) job.dcount[(size_t)s * K + r] = job.series[s].p.lmin <= 1 ? w.count[r] : w.dcount[r];
+            // fused window mode resolves a series only when every target hit
+            if (window) job.hit[(size_t)s * K + r] = (w.win_hit[r] && (!fused || w.range_ok)) ? 1 : 0;
         }
         if (job.mode & MODE_SWEEP) {
             const uint32_t Kp = w.Kp;
@@ -768,22 +767,51 @@ void finish_lines(Job& job)
     }
 }
 
-// Exact thresholds (plain or windowed selection) with the line values riding
-// along, then RR and DET at them: no separate sweep.
+// Exact thresholds (plain or windowed counting passes) and RR, DET at them.
+// Normally the last pass is the range sweep, which finishes the thresholds and
+// counts C and D in the same pass.  With many targets its histograms do not
+// fit the LDS: then the thresholds are selected completely first and a sweep
+// at them follows.  stat_passes counts every full pass over the pairs.
 rqa_status select_and_sweep(rqa_ctx* c, Job& job)
 {
-    job.mode = MODE_FUSED;
     rqa_status st;
+    if (sweep_lds_bytes(2 * job.K + 1, true) <= c->max_lds) {
+        job.mode = MODE_FUSED;
+        if (job.sel == 0) {
+            c->stat_passes = 3;
+            c->stat_fallback = 0;
+            c->stat_missed = 0;
+            st = run_job(c, job);
+        } else {
+            st = select_windowed(c, job);
+        }
+        if (st) return st;
+        finish_lines(job);
+        return RQA_OK;
+    }
     if (job.sel == 0) {
-        c->stat_passes = 3;
+        job.mode = MODE_BOTH;
+        c->stat_passes = 4;
         c->stat_fallback = 0;
         c->stat_missed = 0;
-        st = run_job(c, job);
-    } else {
-        st = select_windowed(c, job);
+        return run_job(c, job);
     }
-    if (st) return st;
-    finish_lines(job);
+    job.mode = MODE_SELECT;
+    if ((st = select_windowed(c, job))) return st;
+    Job sw;
+    sw.base = job.base;
+    sw.K = job.K;
+    sw.mode = MODE_SWEEP;
+    sw.series = job.series;
+    sw.eps_bits.resize(job.eps.size());
+    std::memcpy(sw.eps_bits.data(), job.eps.data(), sizeof(uint32_t) * job.eps.size());
+    if ((st = run_job(c, sw))) return st;
+    c->stat_passes += 1;
+    job.count = sw.count;
+    job.rr = sw.rr;
+    job.det = sw.det;
+    job.det_mean = sw.det_mean;
+    job.M = sw.M;
     return RQA_OK;
 }
 
@@ -859,11 +887,13 @@ rqa_status tune_job(rqa_ctx* c, Job& job, uint32_t* seg_out, uint32_t* chunk_out
     }
     rqa_status st = RQA_OK;
     uint32_t last_seg = 0;
+    // tune the path the calls take (see select_and_sweep)
+    const int mode = (job.mode == MODE_FUSED && sweep_lds_bytes(2 * K + 1, true) > c->max_lds) ? MODE_BOTH : job.mode;
     for (auto& kv : buckets) {
         Job sub;
         sub.base = job.base;
         sub.K = K;
-        sub.mode = job.mode;
+        sub.mode = mode;
         uint64_t L0 = 0;
         for (size_t i = 0; i < kv.second.size() && i < 64; ++i) {
             const uint32_t s = kv.second[i];
@@ -889,10 +919,12 @@ rqa_status tune_job(rqa_ctx* c, Job& job, uint32_t* seg_out, uint32_t* chunk_out
     if (!st) {
         c->seg = 0;  // the table just filled
         double best = 1e300;
+        Job whole = job;
+        whole.mode = mode;
         for (uint32_t CT : CHUNK_CANDIDATES) {
             c->chunk_tiles = CT;
             double ms;
-            if ((st = time_job(c, job, 2, &ms))) break;
+            if ((st = time_job(c, whole, 2, &ms))) break;
             if (ms < best) { best = ms; best_chunk = CT; }
         }
     }

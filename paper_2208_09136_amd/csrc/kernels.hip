@@ -343,171 +343,70 @@ __device__ __forceinline__ void wave_add(unsigned long long* base, uint32_t idx,
     }
 }
 
-// ------------------------------------------------------------------ selection
-
-// Line value of a cell: the smallest threshold at which the cell lies on a
-// diagonal line of at least lmin recurrences (Eq. 4 and the line definition
-// after it), i.e. the minimum, over the windows of lmin consecutive cells that
-// contain it, of the window's largest key.  Cells outside the diagonal have
-// key LINE_INF and recur at no threshold.  For lmin = 2 the line value is
-// max(key_t, min(key_{t-1}, key_{t+1})).  The recurrences on lines of length
-// >= lmin at threshold eps number D(eps) = #{line value <= eps}, so the line
-// values can be histogrammed and refined next to the keys and D is known at
-// the exact threshold as soon as the threshold is.  Keys are non-negative
-// floats, so their bit patterns order like their values; LINE_INF lies above
-// every key, +inf included.
-constexpr uint32_t LINE_INF = 0xFFFFFFFFu;
-
-// Line-value classes of the counting kernels: none (keys only), lmin = 2
-// (walker path), any lmin (per-cell path with rings).
-constexpr int LV_NONE = 0, LV_2 = 1, LV_ANY = 2;
-
-// Key bit pattern of cell x on the lane's diagonal; LINE_INF outside it.
-template <int NORM, int MC, int TC>
-__device__ __forceinline__ uint32_t key_or_inf(const SeriesScalars& sd, const TileGeo& g, int x)
+// wave_add kept out of line: the range sweep calls it rarely from deeply
+// unrolled loops, whose registers would otherwise spill
+__device__ __attribute__((noinline)) void fine_add(unsigned long long* base, uint32_t idx, bool active)
 {
-    const bool ok = (x >= 0) && (x < g.len);
-    const int i = ok ? x : 0;
-    const int j = ok ? x + g.d : g.d0;
-    const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, i, j, sd.m, sd.tau));
-    return ok ? u : LINE_INF;
+    wave_add(base, idx, active);
 }
 
+// ------------------------------------------------------------------ selection
+
 // Shared tile driver of the counting passes.  For every cell of the lane's
-// diagonal in the tile: body.look(key) (LDS table reads, issued for a whole
-// block of cells first), then body.count(key, look); with line values
-// (LV != LV_NONE) also body.countL(line value, body.look(line value)).
-template <int NORM, int MC, int TC, int LV, class Body>
+// diagonal in the tile: look = body.look(key) (LDS table reads, issued for a
+// whole block of keys first), then body.count(key, look).
+template <int NORM, int MC, int TC, class Body>
 __device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t tile_id, int lane, Body& body)
 {
     const TileGeo g = tile_geo(sd, tile_id, lane);
-    constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0) && LV != LV_ANY;
+    constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
     if constexpr (kFast) {
         constexpr int TW = MC == 1 ? 1 : TC;
         constexpr int HU = walk_block<NORM, MC, TW>();
         if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
             // interior: every lane's diagonal covers [t0, t1 + WALK_SLACK]
-            if constexpr (LV == LV_NONE) {
-                walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
-                    uint32_t lk[HU];
+            walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                uint32_t lk[HU];
 #pragma unroll
-                    for (int u = 0; u < HU; ++u) lk[u] = body.look(k[u]);
+                for (int u = 0; u < HU; ++u) lk[u] = body.look(k[u]);
 #pragma unroll
-                    for (int u = 0; u < HU; ++u)
-                        if (u < valid) body.count(k[u], lk[u]);
-                });
-            } else {
-                // the walk runs one cell ahead: block keys k[] are the right
-                // neighbours of the cells counted in the block
-                uint32_t um1 = key_or_inf<NORM, MC, TC>(sd, g, g.t0 - 1);
-                uint32_t u0 = key_or_inf<NORM, MC, TC>(sd, g, g.t0);
-                walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
-                    uint32_t c[HU], v[HU], lc[HU], lv[HU];
-#pragma unroll
-                    for (int u = 0; u < HU; ++u) {
-                        const uint32_t left = u == 0 ? um1 : (u == 1 ? u0 : k[u - 2]);
-                        c[u] = u == 0 ? u0 : k[u - 1];
-                        v[u] = max(c[u], min(left, k[u]));
-                    }
-#pragma unroll
-                    for (int u = 0; u < HU; ++u) {
-                        lc[u] = body.look(c[u]);
-                        lv[u] = body.look(v[u]);
-                    }
-#pragma unroll
-                    for (int u = 0; u < HU; ++u)
-                        if (u < valid) {
-                            body.count(c[u], lc[u]);
-                            body.countL(v[u], lv[u]);
-                        }
-                    um1 = k[HU - 2];
-                    u0 = k[HU - 1];
-                });
-            }
+                for (int u = 0; u < HU; ++u)
+                    if (u < valid) body.count(k[u], lk[u]);
+            });
             return;
         }
     }
-    if constexpr (LV == LV_NONE) {
-        for (int x = g.t0; x < g.t1; ++x) {
-            if (x < g.len) {
-                const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau));
-                body.count(u, body.look(u));
-            }
-        }
-    } else if constexpr (LV == LV_2) {
-        uint32_t um1 = key_or_inf<NORM, MC, TC>(sd, g, g.t0 - 1);
-        uint32_t u0 = key_or_inf<NORM, MC, TC>(sd, g, g.t0);
-        for (int x = g.t0; x < g.t1; ++x) {
-            const uint32_t up1 = key_or_inf<NORM, MC, TC>(sd, g, x + 1);
-            if (x < g.len) {
-                const uint32_t v = max(u0, min(um1, up1));
-                body.count(u0, body.look(u0));
-                body.countL(v, body.look(v));
-            }
-            um1 = u0;
-            u0 = up1;
-        }
-    } else {
-        // any lmin <= LMIN_MAX: rings of the last lmin keys and of the last
-        // lmin window maxima; the counted cell lags the newest key by h = lmin-1
-        const int h = sd.lmin - 1;
-        uint32_t rr[LMIN_MAX], ww[LMIN_MAX];
-#pragma unroll
-        for (int i = 0; i < LMIN_MAX; ++i) { rr[i] = LINE_INF; ww[i] = LINE_INF; }
-        for (int x = g.t0 - h; x < g.t1 + h; ++x) {
-            const uint32_t r = key_or_inf<NORM, MC, TC>(sd, g, x);
-#pragma unroll
-            for (int i = 0; i < LMIN_MAX - 1; ++i) rr[i] = rr[i + 1];
-            rr[LMIN_MAX - 1] = r;
-            uint32_t wmax = 0, cell = LINE_INF;
-#pragma unroll
-            for (int i = 0; i < LMIN_MAX; ++i) {
-                if (i >= LMIN_MAX - 1 - h) wmax = max(wmax, rr[i]);
-                if (i == LMIN_MAX - 1 - h) cell = rr[i];
-            }
-#pragma unroll
-            for (int i = 0; i < LMIN_MAX - 1; ++i) ww[i] = ww[i + 1];
-            ww[LMIN_MAX - 1] = wmax;
-            const int xc = x - h;
-            if (xc >= g.t0 && xc < g.len) {
-                uint32_t v = LINE_INF;
-#pragma unroll
-                for (int i = 0; i < LMIN_MAX; ++i)
-                    if (i >= LMIN_MAX - 1 - h) v = min(v, ww[i]);
-                body.count(cell, body.look(cell));
-                body.countL(v, body.look(v));
-            }
+    for (int x = g.t0; x < g.t1; ++x) {
+        if (x < g.len) {
+            const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau));
+            body.count(u, body.look(u));
         }
     }
 }
 
 // Bytes of a selection pass's LDS tables and bins; the work-queue word follows.
-__host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G, bool lines)
+__host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G)
 {
-    const size_t nb = lines ? 2 : 1;
-    if (pass == 1) return nb * SEL_N1 * 4;
-    if (pass == 2) return SEL_N1 + nb * (size_t)G * SEL_N2 * 4;
+    if (pass == 1) return SEL_N1 * 4;
+    if (pass == 2) return SEL_N1 * 2 + (size_t)G * SEL_N2 * 4;
     return SEL_N1 + (size_t)K * SEL_N2;
 }
 
-// Pass 1: histogram of the top SEL_B1 bits of every key (and line value).
-template <int NORM, int MC, int TC, int LV>
+// Pass 1: histogram of the top SEL_B1 bits of every key.
+template <int NORM, int MC, int TC>
 struct SelPass1 {
-    uint32_t* bins;   // LDS [SEL_N1] (keys), then [SEL_N1] (line values)
+    uint32_t* bins;   // LDS [SEL_N1]
     uint64_t* h1;     // global [S][SEL_N1]
-    uint64_t* h1L;
     bool active = true;
-    static constexpr bool L = LV != LV_NONE;
     __device__ void begin(uint32_t)
     {
-        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * SEL_N1; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
-        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * SEL_N1; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) {
             const uint32_t v = bins[i];
-            uint64_t* dst = i < SEL_N1 ? &h1[(size_t)s * SEL_N1 + i] : &h1L[(size_t)s * SEL_N1 + i - SEL_N1];
-            if (v) atomicAdd((unsigned long long*)dst, (unsigned long long)v);
+            if (v) atomicAdd((unsigned long long*)&h1[(size_t)s * SEL_N1 + i], (unsigned long long)v);
         }
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
@@ -515,73 +414,64 @@ struct SelPass1 {
     {
         atomicAdd(&bins[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)], 1u);
     }
-    __device__ __forceinline__ void countL(uint32_t v, uint32_t) const
-    {
-        atomicAdd(&bins[SEL_N1 + __builtin_amdgcn_ubfe(v, SEL_SH1, SEL_B1)], 1u);
-    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-// Pass 2: for keys (line values) whose pass-1 bucket holds a target (slot in
-// [lo, hi)), histogram the next SEL_B2 bits per slot.
-template <int NORM, int MC, int TC, int LV>
+// Pass 2: for keys whose pass-1 bucket holds a target (slot in [lo, hi)),
+// histogram the next SEL_B2 bits per slot.
+constexpr uint16_t NO_BIN = 0xFFFF;
+template <int NORM, int MC, int TC>
 struct SelPass2 {
-    uint8_t* sT1;     // LDS [SEL_N1]
-    uint32_t* bins;   // LDS [G][SEL_N2] (keys), then [G][SEL_N2] (line values)
+    uint16_t* sOff;   // LDS [SEL_N1]: first bin of the bucket's slot in this group, or NO_BIN
+    uint32_t* bins;   // LDS [G][SEL_N2]
     const uint8_t* T1;
     const SeriesWork* works;
     uint64_t* h2;     // global [S][K][SEL_N2]
-    uint64_t* h2L;
     uint32_t K, G, lo, hi;
     bool active = true;
-    static constexpr bool L = LV != LV_NONE;
     __device__ void begin(uint32_t s)
     {
         const uint32_t ns = works[s].nslots2;
         hi = min(lo + G, ns);
         active = lo < ns;
-        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
-        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * G * SEL_N2; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) {
+            const uint32_t t = T1[(size_t)s * SEL_N1 + i];
+            sOff[i] = (t >= lo && t < hi) ? (uint16_t)((t - lo) * SEL_N2) : NO_BIN;
+        }
+        for (uint32_t i = threadIdx.x; i < G * SEL_N2; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
         if (!active) return;
         const uint32_t n = (hi - lo) * SEL_N2;
-        for (int part = 0; part < (L ? 2 : 1); ++part) {
-            uint64_t* dst = (part ? h2L : h2) + ((size_t)s * K + lo) * SEL_N2;
-            const uint32_t* src = bins + (size_t)part * G * SEL_N2;
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-                const uint32_t v = src[i];
-                if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
-            }
+        uint64_t* dst = h2 + ((size_t)s * K + lo) * SEL_N2;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t v = bins[i];
+            if (v) atomicAdd((unsigned long long*)&dst[i], (unsigned long long)v);
         }
     }
-    // slot of the value's pass-1 bucket relative to this group (>= span: none)
+    // first bin of the key's pass-1 bucket's slot (NO_BIN: not a target bucket of this group)
     __device__ __forceinline__ uint32_t look(uint32_t u) const
     {
-        return (uint32_t)sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)] - lo;
+        return sOff[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
     }
-    __device__ __forceinline__ void count(uint32_t u, uint32_t rel) const
+    __device__ __forceinline__ void count(uint32_t u, uint32_t off) const
     {
-        if (rel < hi - lo) atomicAdd(&bins[rel * SEL_N2 + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)], 1u);
-    }
-    __device__ __forceinline__ void countL(uint32_t v, uint32_t rel) const
-    {
-        if (rel < hi - lo) atomicAdd(&bins[(G + rel) * SEL_N2 + __builtin_amdgcn_ubfe(v, SEL_SH2, SEL_B2)], 1u);
+        if (off != NO_BIN) atomicAdd(&bins[off + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)], 1u);
     }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-// Pass 3: for keys (line values) whose 20-bit prefix holds a target, count
-// the last SEL_B3 bits per pass-3 slot directly in global memory (few
-// qualify).
-template <int NORM, int MC, int TC, int LV>
+// Pass 3 (selection only): for keys whose 21-bit prefix holds a target,
+// count the last SEL_B3 bits per pass-3 slot directly in global memory (few
+// keys qualify).
+template <int NORM, int MC, int TC>
 struct SelPass3 {
     uint8_t* sT1;     // LDS [SEL_N1]
     uint8_t* sT2;     // LDS [K][SEL_N2]
@@ -589,10 +479,8 @@ struct SelPass3 {
     const uint8_t* T2;
     const SeriesWork* works;
     uint64_t* h3;     // global [S][K][SEL_N3]
-    uint64_t* h3L;
     uint32_t K;
     unsigned long long* dst;
-    unsigned long long* dstL;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
@@ -600,10 +488,9 @@ struct SelPass3 {
         for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
         for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) sT2[i] = T2[(size_t)s * K * SEL_N2 + i];
         dst = (unsigned long long*)(h3 + (size_t)s * K * SEL_N3);
-        dstL = LV != LV_NONE ? (unsigned long long*)(h3L + (size_t)s * K * SEL_N3) : nullptr;
     }
     __device__ void flush(uint32_t) {}
-    // pass-3 slot of the value's 20-bit prefix (NO_SLOT: none)
+    // pass-3 slot of the key's 21-bit prefix (NO_SLOT: none)
     __device__ __forceinline__ uint32_t look(uint32_t u) const
     {
         const uint32_t s2 = sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
@@ -613,62 +500,51 @@ struct SelPass3 {
     {
         wave_add(dst, s3 * SEL_N3 + (u & (SEL_N3 - 1)), s3 != NO_SLOT);
     }
-    __device__ __forceinline__ void countL(uint32_t v, uint32_t s3) const
-    {
-        wave_add(dstL, s3 * SEL_N3 + (v & (SEL_N3 - 1)), s3 != NO_SLOT);
-    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-template <int PASS, int NORM, int MC, int TC, int LV>
+template <int PASS, int NORM, int MC, int TC>
 __global__ void __launch_bounds__(1024)
 k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
          uint32_t* __restrict__ tickets, SeriesWork* __restrict__ works, const uint8_t* __restrict__ T1,
-         const uint8_t* __restrict__ T2, uint64_t* __restrict__ hist, uint64_t* __restrict__ histL, uint32_t K,
-         uint32_t G)
+         const uint8_t* __restrict__ T2, uint64_t* __restrict__ hist, uint32_t K, uint32_t G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* ticket = tickets + blockIdx.y;
-    uint32_t* slot = (uint32_t*)(smem + select_lds_bytes_dev(PASS, K, G, LV != LV_NONE));
+    uint32_t* slot = (uint32_t*)(smem + select_lds_bytes_dev(PASS, K, G));
     if constexpr (PASS == 1) {
-        SelPass1<NORM, MC, TC, LV> body{(uint32_t*)smem, hist, histL};
+        SelPass1<NORM, MC, TC> body{(uint32_t*)smem, hist};
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else if constexpr (PASS == 2) {
-        SelPass2<NORM, MC, TC, LV> body;
-        body.sT1 = (uint8_t*)smem;
-        body.bins = (uint32_t*)(smem + SEL_N1);
+        SelPass2<NORM, MC, TC> body;
+        body.sOff = (uint16_t*)smem;
+        body.bins = (uint32_t*)(smem + SEL_N1 * 2);
         body.T1 = T1;
         body.works = works;
         body.h2 = hist;
-        body.h2L = histL;
         body.K = K;
         body.G = G;
         body.lo = blockIdx.y * G;
         body.hi = body.lo;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else {
-        SelPass3<NORM, MC, TC, LV> body;
+        SelPass3<NORM, MC, TC> body;
         body.sT1 = (uint8_t*)smem;
         body.sT2 = (uint8_t*)(smem + SEL_N1);
         body.T1 = T1;
         body.T2 = T2;
         body.works = works;
         body.h3 = hist;
-        body.h3L = histL;
         body.K = K;
         body.dst = nullptr;
-        body.dstL = nullptr;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     }
 }
 
-size_t select_lds_bytes(int pass, uint32_t K, uint32_t G, bool lines)
-{
-    return select_lds_bytes_dev(pass, K, G, lines) + 16;
-}
+size_t select_lds_bytes(int pass, uint32_t K, uint32_t G) { return select_lds_bytes_dev(pass, K, G) + 16; }
 
 static int mclass_of(uint32_t m, uint32_t tau)
 {
@@ -680,13 +556,6 @@ static int mclass_of(uint32_t m, uint32_t tau)
 
 int select_variant_of(uint32_t norm, uint32_t m, uint32_t tau) { return (int)norm * NUM_MCLASS + mclass_of(m, tau); }
 
-int lines_variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
-{
-    if (lmin <= 1) return select_variant_of(norm, m, tau);
-    if (lmin == 2) return LV_2 * NUM_SELECT_VARIANTS + select_variant_of(norm, m, tau);
-    return LV_ANY * NUM_SELECT_VARIANTS + (int)norm * NUM_MCLASS;
-}
-
 int variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
 {
     const int lc = (lmin == 1) ? 1 : (lmin == 2) ? 2 : 0;
@@ -694,38 +563,24 @@ int variant_of(uint32_t norm, uint32_t m, uint32_t tau, uint32_t lmin)
 }
 
 using SelFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint8_t*,
-                       const uint8_t*, uint64_t*, uint64_t*, uint32_t, uint32_t);
+                       const uint8_t*, uint64_t*, uint32_t, uint32_t);
 
-template <int PASS, int NORM, int LV>
+template <int PASS, int NORM>
 static SelFn select_fn_n(int mclass)
 {
-    if constexpr (LV == LV_ANY) {
-        return k_select<PASS, NORM, 0, 0, LV>;
-    } else {
-        switch (mclass) {
-        case 1: return k_select<PASS, NORM, 1, 0, LV>;
-        case 2: return k_select<PASS, NORM, 3, 3, LV>;
-        case 3: return k_select<PASS, NORM, 3, 5, LV>;
-        default: return k_select<PASS, NORM, 0, 0, LV>;
-        }
+    switch (mclass) {
+    case 1: return k_select<PASS, NORM, 1, 0>;
+    case 2: return k_select<PASS, NORM, 3, 3>;
+    case 3: return k_select<PASS, NORM, 3, 5>;
+    default: return k_select<PASS, NORM, 0, 0>;
     }
-}
-
-template <int PASS, int LV>
-static SelFn select_fn_lv(int v)
-{
-    const int norm = v / NUM_MCLASS, mc = v % NUM_MCLASS;
-    return norm == RQA_NORM_MAX ? select_fn_n<PASS, RQA_NORM_MAX, LV>(mc)
-                                : select_fn_n<PASS, RQA_NORM_EUCLIDEAN, LV>(mc);
 }
 
 template <int PASS>
 static SelFn select_fn(int variant)
 {
-    const int lv = variant / NUM_SELECT_VARIANTS, v = variant % NUM_SELECT_VARIANTS;
-    if (lv == LV_2) return select_fn_lv<PASS, LV_2>(v);
-    if (lv == LV_ANY) return select_fn_lv<PASS, LV_ANY>(v);
-    return select_fn_lv<PASS, LV_NONE>(v);
+    const int norm = variant / NUM_MCLASS, mc = variant % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? select_fn_n<PASS, RQA_NORM_MAX>(mc) : select_fn_n<PASS, RQA_NORM_EUCLIDEAN>(mc);
 }
 
 static SelFn select_fn_pass(int pass, int variant)
@@ -738,12 +593,10 @@ static SelFn select_fn_pass(int pass, int variant)
 hipError_t launch_select_pass(hipStream_t st, const DevBufs& b, int pass, int variant, uint32_t grid,
                               uint32_t block, uint32_t groups, uint32_t G, uint32_t ticket_base)
 {
-    const bool lines = variant >= NUM_SELECT_VARIANTS;
-    const size_t lds = select_lds_bytes(pass, b.K, G, lines);
+    const size_t lds = select_lds_bytes(pass, b.K, G);
     uint64_t* hist = pass == 1 ? b.h1 : pass == 2 ? b.h2 : b.h3;
-    uint64_t* histL = pass == 1 ? b.h1L : pass == 2 ? b.h2L : b.h3L;
     hipLaunchKernelGGL(select_fn_pass(pass, variant), dim3(grid, groups), dim3(block), lds, st, b.sd, b.S,
-                       b.nchunks, b.chunk_tiles, b.tickets + ticket_base, b.work, b.T1, b.T2, hist, histL, b.K, G);
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket_base, b.work, b.T1, b.T2, hist, b.K, G);
     return hipGetLastError();
 }
 
@@ -822,11 +675,9 @@ __device__ __forceinline__ uint32_t index_of(const uint32_t* v, uint32_t n, uint
     return lo;
 }
 
-// After pass 1: locate each target's bucket, assign pass-2 slots, fill T1;
-// with line values (h1L non-null) count those below each target's bucket.
+// After pass 1: locate each target's bucket, assign pass-2 slots, fill T1.
 __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               uint8_t* __restrict__ T1, const uint64_t* __restrict__ h1,
-                                               const uint64_t* __restrict__ h1L)
+                                               uint8_t* __restrict__ T1, const uint64_t* __restrict__ h1)
 {
     __shared__ uint64_t cum[SEL_N1];
     __shared__ uint32_t uniq[RQA_MAX_K];
@@ -852,21 +703,12 @@ __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sd
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) t1[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.nslots2 = nu;
-    if (h1L) {
-        __syncthreads();
-        block_cumsum(h1L + (size_t)s * SEL_N1, cum, SEL_N1);
-        for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
-            const uint32_t b = w.prefix[r];
-            w.belowL[r] = b ? cum[b - 1] : 0;
-        }
-    }
 }
 
 // After pass 2: resolve SEL_B2 more bits per target, assign pass-3 slots,
 // fill T2 (per pass-2 slot and sub-bucket).
 __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2,
-                                               const uint64_t* __restrict__ h2L)
+                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2)
 {
     __shared__ uint32_t uniq[RQA_MAX_K];
     __shared__ uint32_t nuniq;
@@ -887,12 +729,6 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
         }
         if (c == SEL_N2) { c = SEL_N2 - 1; atomicOr(&w.status, 2u); }
         w.below[r] += run;
-        if (h2L) {
-            const uint64_t* hl = h2L + ((size_t)s * K + w.slot[r]) * SEL_N2;
-            uint64_t runL = 0;
-            for (uint32_t i = 0; i < c; ++i) runL += hl[i];
-            w.belowL[r] += runL;
-        }
         w.prefix[r] = (w.prefix[r] << SEL_B2) | c;
         uniq[r] = w.prefix[r];
     }
@@ -911,7 +747,7 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
 
 // After pass 3: the last SEL_B3 bits give the threshold; count = #{key <= eps}.
 __global__ void __launch_bounds__(256) k_scan3(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               const uint64_t* __restrict__ h3, const uint64_t* __restrict__ h3L)
+                                               const uint64_t* __restrict__ h3)
 {
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
@@ -928,39 +764,32 @@ __global__ void __launch_bounds__(256) k_scan3(const SeriesDesc* __restrict__ sd
         if (c == SEL_N3) { c = SEL_N3 - 1; atomicOr(&w.status, 4u); }
         w.eps_bits[r] = (w.prefix[r] << SEL_B3) | c;
         w.count[r] = w.below[r] + run + h[c];
-        if (h3L) {
-            const uint64_t* hl = h3L + ((size_t)s * K + w.slot[r]) * SEL_N3;
-            uint64_t runL = 0;
-            for (uint32_t i = 0; i <= c; ++i) runL += hl[i];
-            w.dcount[r] = w.belowL[r] + runL;
-        }
     }
 }
 
 hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass)
 {
-    const bool L = b.lines != 0;
-    if (pass == 1)
-        hipLaunchKernelGGL(k_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T1, b.h1, L ? b.h1L : nullptr);
-    else if (pass == 2)
-        hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2, L ? b.h2L : nullptr);
-    else
-        hipLaunchKernelGGL(k_scan3, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.h3, L ? b.h3L : nullptr);
+    if (pass == 1) hipLaunchKernelGGL(k_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T1, b.h1);
+    else if (pass == 2) hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2);
+    else hipLaunchKernelGGL(k_scan3, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.h3);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ sweep
 
-// Rank of a key among the distinct sorted thresholds e_0 < ... < e_{Kp-1}:
-// rho = #{e < key}.  The pair recurs at threshold j iff rho <= j.  The bucket
-// of the key (clamped to [e_0, e_{Kp-1}]) gives #{e below the bucket} and the
-// bucket's first threshold; buckets holding several thresholds fall back to
-// comparing against each of them.
+// Rank of a key among the sorted thresholds e_0 < ... < e_{Kp-1}, plus a
+// per-series base z: rho = z + #{e < key}.  Given thresholds: z = 0 and the
+// pair recurs at threshold j iff rho <= j.  Range sweep: the thresholds are
+// the group boundaries (first value - 1, last value) and z = 1 when the first
+// group starts at key 0, so rho is odd exactly for keys inside a group,
+// group (rho - 1) / 2.  The bucket of the key (clamped to [e_0, e_{Kp-1}])
+// gives the rank below the bucket and the bucket's first threshold; buckets
+// holding several thresholds compare each of them.
 struct RhoCtx {
     const uint2* table;     // LDS [RHO_TABLE]: x = first threshold in bucket (or ~0), y = rank base
-    const uint32_t* es;     // LDS [Kp] distinct thresholds
+    const uint32_t* es;     // LDS [Kp] thresholds
     float emin, emax;       // smallest and largest threshold
-    uint32_t shift, Kp;
+    uint32_t shift, Kp, z;
 };
 
 // MULTI: some bucket holds more than one threshold (rare; flagged per series).
@@ -975,21 +804,49 @@ __device__ __forceinline__ uint32_t rho_of(uint32_t u, const RhoCtx& c)
         if (e.y >= RHO_MULTI) {
             const uint32_t base = e.y & 0xFFFFu, cnt = e.y >> 16;
             r = base;
-            for (uint32_t i = 0; i < cnt; ++i) r += (u > c.es[base + i]) ? 1u : 0u;
+            for (uint32_t i = 0; i < cnt; ++i) r += (u > c.es[base - c.z + i]) ? 1u : 0u;
         }
     }
     return r;
 }
 
-// Line rank lambda_t: the smallest distinct-threshold index at which cell t
-// lies on a diagonal line of length >= lmin, i.e. the minimum over windows of
-// lmin consecutive cells containing t of the window's largest rho (cells
-// outside the diagonal have rho = Kp).  lmin = 2: max(rho_t, min(rho_{t-1},
-// rho_{t+1})).
+// Range sweep: buckets of 2^shift bit patterns hold up to two boundaries
+// (x, y) and the rank base z (z + boundaries below the bucket); w > 0 marks a
+// bucket with w > 2 boundaries, compared one by one (rare).
+struct RangeCtx {
+    const uint4* table;     // LDS [RANGE_TABLE]
+    const uint32_t* es;     // LDS [Kp] boundaries
+    float emin, emax;
+    uint32_t shift, Kp, z;
+};
+
+template <bool MULTI>
+__device__ __forceinline__ uint32_t rank_of(uint32_t u, const RangeCtx& c)
+{
+    const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
+    const uint4 e = c.table[__builtin_amdgcn_ubfe(cl, c.shift, RANGE_BITS)];
+    uint32_t r = e.z + (u > e.x ? 1u : 0u) + (u > e.y ? 1u : 0u);
+    if constexpr (MULTI) {
+        if (e.w) {
+            r = e.z;
+            for (uint32_t i = 0; i < e.w; ++i) r += (u > c.es[e.z - c.z + i]) ? 1u : 0u;
+        }
+    }
+    return r;
+}
+
+// Line rank lambda_t: the smallest threshold index at which cell t lies on a
+// diagonal line of length >= lmin, i.e. the minimum over windows of lmin
+// consecutive cells containing t of the window's largest rho (cells outside
+// the diagonal have rho = Kp).  lmin = 2: max(rho_t, min(rho_{t-1},
+// rho_{t+1})).  Because rho is monotone in the key, lambda is also the rank
+// of the cell's line value: the same expression over keys, i.e. the smallest
+// threshold at which the cell lies on such a line (Eq. 4 and the line
+// definition after it).
 template <int NORM, int MC, int TC, int LMC>
 struct SweepBody {
     uint2* stab;          // LDS [RHO_TABLE]
-    uint32_t* ses;        // LDS [RQA_MAX_K]
+    uint32_t* ses;        // LDS [RANK_MAX]
     uint32_t* brho;       // LDS [Kcap+1][64]: row Kp collects cells that recur at no threshold
     uint32_t* blam;       // LDS [Kcap+1][64]
     const uint2* rtab;    // global [S][RHO_TABLE]
@@ -1004,7 +861,7 @@ struct SweepBody {
     {
         const SeriesWork& w = works[s];
         for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RHO_TABLE + i];
-        for (uint32_t i = threadIdx.x; i < RQA_MAX_K; i += blockDim.x) ses[i] = w.esorted[i];
+        for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) ses[i] = w.esorted[i];
         for (uint32_t i = threadIdx.x; i < (Kcap + 1) * TILE_W; i += blockDim.x) { brho[i] = 0u; blam[i] = 0u; }
         rc.table = stab;
         rc.es = ses;
@@ -1012,6 +869,7 @@ struct SweepBody {
         rc.emax = __uint_as_float(uniform(w.emax));
         rc.shift = uniform(w.shift);
         rc.Kp = uniform(w.Kp);
+        rc.z = 0;
         multi = uniform(w.multi) != 0;
     }
     __device__ void flush(uint32_t s)
@@ -1134,11 +992,242 @@ struct SweepBody {
     }
 };
 
-// LDS of the sweep: rank table, thresholds, two per-lane histograms with a
-// spare row, then the work-queue word.
-__host__ __device__ __forceinline__ size_t sweep_lds_bytes_dev(uint32_t Kcap)
+// Range sweep.  The ranks are taken against the group boundaries (odd rank:
+// inside group rank/2, see RangeCtx), and only the line ranks are
+// histogrammed: C comes from the counting passes plus the fine counters, D
+// from the line ranks below the target's group plus the fine counters of
+// line values inside it.  A key or line value inside a group adds one to
+// the group's fine counter at its offset from the group start (global
+// memory, rare).  lmin = 1 needs no line values (D = C).
+template <int NORM, int MC, int TC, int LMC>
+struct RangeBody {
+    uint4* stab;          // LDS [RANGE_TABLE]
+    uint32_t* ses;        // LDS [RANK_MAX]
+    uint32_t* blam;       // LDS [rows+1][64]: the last row collects cells outside the diagonal
+    uint32_t* sglo;       // LDS [RQA_MAX_K + 1] group starts
+    uint32_t* sgoff;      // LDS [RQA_MAX_K + 1] group fine offsets
+    const uint4* rtab;    // global [S][RANGE_TABLE]
+    SeriesWork* works;
+    uint64_t* fineK;      // global [S][fine_stride]
+    uint64_t* fineL;
+    uint32_t fine_stride;
+    unsigned long long* dk;
+    unsigned long long* dl;
+    uint32_t rows;
+    RangeCtx rc;
+    uint32_t lmin;
+    uint32_t spare;       // rank above every boundary (and of cells outside the diagonal)
+    uint32_t ngroups, nfine;
+    bool multi;
+    bool active = true;
+
+    __device__ void begin(uint32_t s)
+    {
+        const SeriesWork& w = works[s];
+        active = uniform(w.range_ok) != 0;
+        for (uint32_t i = threadIdx.x; i < RANGE_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RANGE_TABLE + i];
+        for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) ses[i] = w.esorted[i];
+        for (uint32_t i = threadIdx.x; i < (rows + 1) * TILE_W; i += blockDim.x) blam[i] = 0u;
+        for (uint32_t i = threadIdx.x; i <= RQA_MAX_K; i += blockDim.x) {
+            sglo[i] = w.g_lo[i];
+            sgoff[i] = w.g_off[i];
+        }
+        rc.table = stab;
+        rc.es = ses;
+        rc.emin = __uint_as_float(uniform(w.emin));
+        rc.emax = __uint_as_float(uniform(w.emax));
+        rc.shift = uniform(w.shift);
+        rc.Kp = uniform(w.Kp);
+        rc.z = uniform(w.zbase);
+        spare = rc.Kp + rc.z;
+        ngroups = uniform(w.ngroups);
+        nfine = active ? uniform(w.nsub) << uniform(w.range_bits) : 0u;
+        multi = uniform(w.multi) != 0;
+        dk = (unsigned long long*)(fineK + (size_t)s * fine_stride);
+        dl = (unsigned long long*)(fineL + (size_t)s * fine_stride);
+    }
+    __device__ void flush(uint32_t s)
+    {
+        if (!active || LMC == 1) return;
+        SeriesWork& w = works[s];
+        for (uint32_t j = threadIdx.x; j < spare; j += blockDim.x) {
+            const uint32_t* row = blam + j * TILE_W;
+            uint64_t sum = 0;
+            for (int l = 0; l < TILE_W; ++l) sum += row[l];
+            if (sum) atomicAdd((unsigned long long*)&w.hlam[j], (unsigned long long)sum);
+        }
+    }
+    __device__ __forceinline__ void emit(uint32_t lam, int lane) const { atomicAdd(&blam[lam * TILE_W + lane], 1u); }
+    // count value x of rank r if r is odd (inside group r/2); group and
+    // counter index are checked, so no rank can address outside the counters
+    __device__ __forceinline__ void fine(unsigned long long* dst, uint32_t r, uint32_t x) const
+    {
+        const uint32_t g = min(r >> 1, ngroups);
+        const uint32_t idx = sgoff[g] + (x - sglo[g]);
+        fine_add(dst, idx, (r & 1u) != 0 && g < ngroups && idx < nfine);
+    }
+    __device__ __forceinline__ uint32_t key_at(const SeriesScalars& sd, const TileGeo& g, int x) const
+    {
+        const bool ok = (x >= 0) && (x < g.len);
+        const int i = ok ? x : 0;
+        const int j = ok ? x + g.d : g.d0;
+        const uint32_t k = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, i, j, sd.m, sd.tau));
+        return ok ? k : 0xFFFFFFFFu;  // outside the diagonal: above every boundary
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ uint32_t rank_at(uint32_t key) const
+    {
+        return key == 0xFFFFFFFFu ? spare : rank_of<MULTI>(key, rc);
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        if (multi) tile_impl<true>(sd, tile_id, lane);
+        else tile_impl<false>(sd, tile_id, lane);
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void tile_impl(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        const TileGeo g = tile_geo(sd, tile_id, lane);
+        constexpr bool kFast = (LMC == 1 || LMC == 2) && MC > 0 && (MC == 1 || TC > 0);
+        constexpr int TW = MC == 1 ? 1 : TC;
+        if constexpr (kFast) {
+            if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
+                // interior: every lane's diagonal covers [t0 - 1, t1 + WALK_SLACK]
+                const RangeCtx c = rc;
+                constexpr int HU = walk_block<NORM, MC, TW>();
+                if constexpr (LMC == 1) {
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                        uint32_t r[HU];
+                        uint32_t acc = 0;
+#pragma unroll
+                        for (int u = 0; u < HU; ++u) {
+                            r[u] = rank_of<MULTI>(k[u], c);
+                            if (u < valid) acc |= r[u];
+                        }
+                        if (__ballot(acc & 1u)) {   // rare: a key of the block lies inside a group
+#pragma unroll
+                            for (int u = 0; u < HU; ++u)
+                                if (u < valid && __ballot(r[u] & 1u)) fine(dk, r[u], k[u]);
+                        }
+                    });
+                } else {
+                    // the walk runs one cell ahead: block keys are the right
+                    // neighbours of the cells counted in the block
+                    uint32_t km1 = key_at(sd, g, g.t0 - 1), k0 = key_at(sd, g, g.t0);
+                    uint32_t rm1 = rank_at<MULTI>(km1), r0 = rank_at<MULTI>(k0);
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                        uint32_t r[HU];
+#pragma unroll
+                        for (int u = 0; u < HU; ++u) r[u] = rank_of<MULTI>(k[u], c);
+                        uint32_t acc = 0;
+#pragma unroll
+                        for (int u = 0; u < HU; ++u) {
+                            if (u < valid) {
+                                const uint32_t cr = u == 0 ? r0 : r[u - 1];
+                                const uint32_t left = u == 0 ? rm1 : (u == 1 ? r0 : r[u - 2]);
+                                const uint32_t lam = max(cr, min(left, r[u]));
+                                emit(lam, lane);
+                                acc |= cr | lam;
+                            }
+                        }
+                        if (__ballot(acc & 1u)) {
+                            // rare: some key or line value of the block lies inside a
+                            // group; walk the block again for the fine counters
+#pragma unroll
+                            for (int u = 0; u < HU; ++u) {
+                                if (u < valid) {
+                                    const uint32_t cr = u == 0 ? r0 : r[u - 1];
+                                    const uint32_t left = u == 0 ? rm1 : (u == 1 ? r0 : r[u - 2]);
+                                    const uint32_t lam = max(cr, min(left, r[u]));
+                                    if (__ballot((cr | lam) & 1u)) {
+                                        const uint32_t ck = u == 0 ? k0 : k[u - 1];
+                                        const uint32_t lk = u == 0 ? km1 : (u == 1 ? k0 : k[u - 2]);
+                                        fine(dk, cr, ck);
+                                        fine(dl, lam, max(ck, min(lk, k[u])));
+                                    }
+                                }
+                            }
+                        }
+                        // state for the next block (only full blocks have one)
+                        km1 = k[HU - 2];
+                        k0 = k[HU - 1];
+                        rm1 = r[HU - 2];
+                        r0 = r[HU - 1];
+                    });
+                }
+                return;
+            }
+        }
+        if constexpr (LMC == 1) {
+            for (int x = g.t0; x < g.t1; ++x) {
+                const uint32_t k = key_at(sd, g, x);
+                const uint32_t r = rank_at<MULTI>(k);
+                if (__ballot(r & 1u)) fine(dk, r, k);
+            }
+        } else if constexpr (LMC == 2) {
+            uint32_t km1 = key_at(sd, g, g.t0 - 1), k0 = key_at(sd, g, g.t0);
+            uint32_t rm1 = rank_at<MULTI>(km1), r0 = rank_at<MULTI>(k0);
+            for (int x = g.t0; x < g.t1; ++x) {
+                const uint32_t kp1 = key_at(sd, g, x + 1);
+                const uint32_t rp1 = rank_at<MULTI>(kp1);
+                const uint32_t lam = max(r0, min(rm1, rp1));
+                emit(lam, lane);
+                if (__ballot((r0 | lam) & 1u)) {
+                    fine(dk, r0, k0);
+                    fine(dl, lam, max(k0, min(km1, kp1)));
+                }
+                km1 = k0;
+                k0 = kp1;
+                rm1 = r0;
+                r0 = rp1;
+            }
+        } else {
+            // general lmin <= LMIN_MAX: rings of the last lmin keys and of the
+            // last lmin window maxima (keys; ranks follow); the counted cell lags
+            // the newest key by h = lmin-1
+            const int h = (int)lmin - 1;
+            uint32_t kk[LMIN_MAX], wk[LMIN_MAX];
+#pragma unroll
+            for (int i = 0; i < LMIN_MAX; ++i) { kk[i] = 0xFFFFFFFFu; wk[i] = 0xFFFFFFFFu; }
+            for (int x = g.t0 - h; x < g.t1 + h; ++x) {
+                const uint32_t key = key_at(sd, g, x);
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX - 1; ++i) kk[i] = kk[i + 1];
+                kk[LMIN_MAX - 1] = key;
+                uint32_t wmax = 0, kold = 0xFFFFFFFFu;
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX; ++i) {
+                    if (i >= LMIN_MAX - 1 - h) wmax = max(wmax, kk[i]);
+                    if (i == LMIN_MAX - 1 - h) kold = kk[i];
+                }
+#pragma unroll
+                for (int i = 0; i < LMIN_MAX - 1; ++i) wk[i] = wk[i + 1];
+                wk[LMIN_MAX - 1] = wmax;
+                if (x >= g.t0 + h) {
+                    uint32_t lkey = 0xFFFFFFFFu;
+#pragma unroll
+                    for (int i = 0; i < LMIN_MAX; ++i)
+                        if (i >= LMIN_MAX - 1 - h) lkey = min(lkey, wk[i]);
+                    const uint32_t rk = rank_at<MULTI>(kold), lam = rank_at<MULTI>(lkey);
+                    emit(lam, lane);
+                    if (__ballot((rk | lam) & 1u)) {
+                        fine(dk, rk, kold);
+                        fine(dl, lam, lkey);
+                    }
+                }
+            }
+        }
+    }
+};
+
+// LDS of the sweeps: rank table, thresholds, per-lane histograms with a spare
+// row (two for given thresholds, one for the range sweep, which also holds
+// the group arrays), then the work-queue word.
+__host__ __device__ __forceinline__ size_t sweep_lds_bytes_dev(uint32_t rows, bool ranges)
 {
-    return RHO_TABLE * sizeof(uint2) + RQA_MAX_K * 4 + 2 * (size_t)(Kcap + 1) * TILE_W * 4;
+    if (ranges)
+        return RANGE_TABLE * sizeof(uint4) + RANK_MAX * 4 + (size_t)(rows + 1) * TILE_W * 4 + 2 * (RQA_MAX_K + 1) * 4;
+    return RHO_TABLE * sizeof(uint2) + RANK_MAX * 4 + 2 * (size_t)(rows + 1) * TILE_W * 4;
 }
 
 template <int NORM, int MC, int TC, int LMC>
@@ -1150,7 +1239,7 @@ k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32
     SweepBody<NORM, MC, TC, LMC> body;
     body.stab = (uint2*)smem;
     body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
-    body.brho = body.ses + RQA_MAX_K;
+    body.brho = body.ses + RANK_MAX;
     body.blam = body.brho + (size_t)(Kcap + 1) * TILE_W;
     body.rtab = rtab;
     body.works = works;
@@ -1159,13 +1248,43 @@ k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32
     // the generic line class reads lmin from the descriptors: launches group
     // series of one lmin
     body.lmin = LMC == 0 ? sds[0].lmin : (uint32_t)LMC;
-    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + sweep_lds_bytes_dev(Kcap)));
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + sweep_lds_bytes_dev(Kcap, false)));
 }
 
-size_t sweep_lds_bytes(uint32_t Kcap) { return sweep_lds_bytes_dev(Kcap) + 16; }
+template <int NORM, int MC, int TC, int LMC>
+__global__ void __launch_bounds__(512)
+k_range_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
+              uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
+              uint32_t rows, uint64_t* __restrict__ fineK, uint64_t* __restrict__ fineL, uint32_t fine_stride)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    RangeBody<NORM, MC, TC, LMC> body;
+    body.stab = (uint4*)smem;
+    body.ses = (uint32_t*)(smem + RANGE_TABLE * sizeof(uint4));
+    body.blam = body.ses + RANK_MAX;
+    body.sglo = body.blam + (size_t)(rows + 1) * TILE_W;
+    body.sgoff = body.sglo + (RQA_MAX_K + 1);
+    body.rtab = (const uint4*)rtab;
+    body.works = works;
+    body.fineK = fineK;
+    body.fineL = fineL;
+    body.fine_stride = fine_stride;
+    body.dk = nullptr;
+    body.dl = nullptr;
+    body.rows = rows;
+    body.ngroups = 0;
+    body.nfine = 0;
+    body.multi = false;
+    body.lmin = LMC == 0 ? sds[0].lmin : (uint32_t)LMC;
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + sweep_lds_bytes_dev(rows, true)));
+}
+
+size_t sweep_lds_bytes(uint32_t rows, bool ranges) { return sweep_lds_bytes_dev(rows, ranges) + 16; }
 
 using SweepFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint2*,
                          uint32_t);
+using RangeFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint2*,
+                         uint32_t, uint64_t*, uint64_t*, uint32_t);
 
 template <int NORM, int MC, int TC>
 static SweepFn sweep_fn_l(int lc)
@@ -1173,6 +1292,14 @@ static SweepFn sweep_fn_l(int lc)
     if (lc == 1) return k_sweep<NORM, MC, TC, 1>;
     if (lc == 2) return k_sweep<NORM, MC, TC, 2>;
     return k_sweep<NORM, MC, TC, 0>;
+}
+
+template <int NORM, int MC, int TC>
+static RangeFn range_fn_l(int lc)
+{
+    if (lc == 1) return k_range_sweep<NORM, MC, TC, 1>;
+    if (lc == 2) return k_range_sweep<NORM, MC, TC, 2>;
+    return k_range_sweep<NORM, MC, TC, 0>;
 }
 
 template <int NORM>
@@ -1186,6 +1313,17 @@ static SweepFn sweep_fn_n(int mclass, int lc)
     }
 }
 
+template <int NORM>
+static RangeFn range_fn_n(int mclass, int lc)
+{
+    switch (mclass) {
+    case 1: return range_fn_l<NORM, 1, 0>(lc);
+    case 2: return range_fn_l<NORM, 3, 3>(lc);
+    case 3: return range_fn_l<NORM, 3, 5>(lc);
+    default: return range_fn_l<NORM, 0, 0>(lc);
+    }
+}
+
 static SweepFn sweep_fn(int variant)
 {
     const int lc = variant % 3, sv = variant / 3;
@@ -1193,27 +1331,85 @@ static SweepFn sweep_fn(int variant)
     return norm == RQA_NORM_MAX ? sweep_fn_n<RQA_NORM_MAX>(mc, lc) : sweep_fn_n<RQA_NORM_EUCLIDEAN>(mc, lc);
 }
 
-hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, uint32_t grid, uint32_t block,
+static RangeFn range_fn(int variant)
+{
+    const int lc = variant % 3, sv = variant / 3;
+    const int norm = sv / NUM_MCLASS, mc = sv % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? range_fn_n<RQA_NORM_MAX>(mc, lc) : range_fn_n<RQA_NORM_EUCLIDEAN>(mc, lc);
+}
+
+static uint32_t sweep_rows(uint32_t K, bool ranges) { return ranges ? 2 * K + 1 : K; }
+
+hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, bool ranges, uint32_t grid, uint32_t block,
                         uint32_t ticket)
 {
-    hipLaunchKernelGGL(sweep_fn(variant), dim3(grid), dim3(block), sweep_lds_bytes(b.K), st, b.sd, b.S,
-                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, b.K);
+    const uint32_t rows = sweep_rows(b.K, ranges);
+    if (ranges)
+        hipLaunchKernelGGL(range_fn(variant), dim3(grid), dim3(block), sweep_lds_bytes(rows, true), st, b.sd, b.S,
+                           b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, rows, b.fineK, b.fineL,
+                           b.fine_stride);
+    else
+        hipLaunchKernelGGL(sweep_fn(variant), dim3(grid), dim3(block), sweep_lds_bytes(rows, false), st, b.sd, b.S,
+                           b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, rows);
     return hipGetLastError();
 }
 
-int sweep_blocks_per_cu(int variant, uint32_t block, size_t lds)
+int sweep_blocks_per_cu(int variant, bool ranges, uint32_t block, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(variant), (int)block, lds) != hipSuccess)
-        return 1;
+    const void* f = ranges ? (const void*)range_fn(variant) : (const void*)sweep_fn(variant);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, (int)block, lds) != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 
-// Per series: distinct sorted thresholds, the caller->distinct map and the
-// rank table.  The table spans the buckets (key >> shift) from the smallest
-// to the largest threshold, with the smallest shift that fits RHO_TABLE
-// buckets; bucket a (mod RHO_TABLE) stores the number of thresholds below
-// a << shift and the first threshold inside the bucket.
+// Rank table of one series over the ascending thresholds es[0..kp) with rank
+// base z: spans the buckets (key >> shift) from es[0] to es[kp-1] with the
+// smallest shift that fits RHO_TABLE buckets; bucket a (mod RHO_TABLE) stores
+// z + the number of thresholds below a << shift, and the first threshold
+// inside the bucket (several inside: flagged, the count in the high half).
+// Called by a whole block after es is complete in LDS.
+__device__ void build_rank_table(SeriesWork& w, const uint32_t* es, uint32_t kp, uint32_t z, uint2* tab,
+                                 uint32_t* s_shift)
+{
+    if (threadIdx.x == 0) {
+        uint32_t sh = 0;
+        while (sh < 31 && (es[kp - 1] >> sh) - (es[0] >> sh) >= RHO_TABLE) ++sh;
+        *s_shift = sh;
+        w.multi = 0u;  // set before the barrier; table entries below may raise it
+    }
+    __syncthreads();
+    const uint32_t sh = *s_shift;
+    const uint32_t emin = es[0], emax = es[kp - 1];
+    for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) w.esorted[i] = (i < kp) ? es[i] : 0xFFFFFFFFu;
+    for (uint32_t i = threadIdx.x; i < RANK_MAX + 2; i += blockDim.x) { w.hrho[i] = 0; w.hlam[i] = 0; }
+    if (threadIdx.x == 0) {
+        w.Kp = kp;
+        w.zbase = z;
+        w.shift = sh;
+        w.emin = emin;
+        w.emax = emax;
+    }
+    const uint32_t a0 = emin >> sh, a1 = emax >> sh;
+    for (uint32_t idx = threadIdx.x; idx < RHO_TABLE; idx += blockDim.x) {
+        const uint32_t a = a0 + ((idx - a0) & (RHO_TABLE - 1));
+        uint2 e = make_uint2(0xFFFFFFFFu, z);
+        if (a <= a1) {
+            const uint64_t lo = (uint64_t)a << sh, hi = (uint64_t)(a + 1) << sh;
+            uint32_t below = 0, inside = 0;
+            for (uint32_t i = 0; i < kp; ++i) {
+                below += (uint64_t)es[i] < lo;
+                inside += ((uint64_t)es[i] >= lo) && ((uint64_t)es[i] < hi);
+            }
+            e.x = inside ? es[below] : 0xFFFFFFFFu;
+            e.y = (inside >= 2) ? ((z + below) | (inside << 16)) : z + below;
+            if (inside >= 2) w.multi = 1u;
+        }
+        tab[idx] = e;
+    }
+}
+
+// Sweep at given thresholds: per series the distinct sorted thresholds, the
+// caller->distinct map and the rank table.
 __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict__ sds,
                                                     SeriesWork* __restrict__ works, uint2* __restrict__ rtab)
 {
@@ -1224,31 +1420,49 @@ __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict
     SeriesWork& w = works[s];
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) es[r] = w.eps_bits[r];
     __syncthreads();
+    if (threadIdx.x == 0) s_kp = sort_unique(es, K);
+    __syncthreads();
+    const uint32_t kp = s_kp;
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.dmap[r] = index_of(es, kp, w.eps_bits[r]);
+    build_rank_table(w, es, kp, 0u, rtab + (size_t)s * RHO_TABLE, &s_shift);
+}
+
+hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
+{
+    hipLaunchKernelGGL(k_sweep_prep, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.rtab);
+    return hipGetLastError();
+}
+
+// Range table of one series over the ascending boundaries es[0..kp) with rank
+// base z: RANGE_TABLE buckets of 2^shift bit patterns from es[0] to
+// es[kp-1]; each holds the first two boundaries inside it (x, y; ~0 when
+// absent), z + the boundaries below it, and w = the count when more than two
+// lie inside (compared one by one).  Called by a whole block.
+__device__ void build_range_table(SeriesWork& w, const uint32_t* es, uint32_t kp, uint32_t z, uint4* tab,
+                                  uint32_t* s_shift)
+{
     if (threadIdx.x == 0) {
-        const uint32_t kp = sort_unique(es, K);
         uint32_t sh = 0;
-        while (sh < 31 && (es[kp - 1] >> sh) - (es[0] >> sh) >= RHO_TABLE) ++sh;
-        s_kp = kp;
-        s_shift = sh;
+        while (sh < 31 && (es[kp - 1] >> sh) - (es[0] >> sh) >= RANGE_TABLE) ++sh;
+        *s_shift = sh;
         w.multi = 0u;  // set before the barrier; table entries below may raise it
     }
     __syncthreads();
-    const uint32_t kp = s_kp, sh = s_shift;
+    const uint32_t sh = *s_shift;
     const uint32_t emin = es[0], emax = es[kp - 1];
-    for (uint32_t i = threadIdx.x; i < RQA_MAX_K; i += blockDim.x) w.esorted[i] = (i < kp) ? es[i] : 0xFFFFFFFFu;
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.dmap[r] = index_of(es, kp, w.eps_bits[r]);
-    for (uint32_t i = threadIdx.x; i <= RQA_MAX_K; i += blockDim.x) { w.hrho[i] = 0; w.hlam[i] = 0; }
+    for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) w.esorted[i] = (i < kp) ? es[i] : 0xFFFFFFFFu;
+    for (uint32_t i = threadIdx.x; i < RANK_MAX + 2; i += blockDim.x) { w.hrho[i] = 0; w.hlam[i] = 0; }
     if (threadIdx.x == 0) {
         w.Kp = kp;
+        w.zbase = z;
         w.shift = sh;
         w.emin = emin;
         w.emax = emax;
     }
     const uint32_t a0 = emin >> sh, a1 = emax >> sh;
-    uint2* tab = rtab + (size_t)s * RHO_TABLE;
-    for (uint32_t idx = threadIdx.x; idx < RHO_TABLE; idx += blockDim.x) {
-        const uint32_t a = a0 + ((idx - a0) & (RHO_TABLE - 1));
-        uint2 e = make_uint2(0xFFFFFFFFu, 0u);
+    for (uint32_t idx = threadIdx.x; idx < RANGE_TABLE; idx += blockDim.x) {
+        const uint32_t a = a0 + ((idx - a0) & (RANGE_TABLE - 1));
+        uint4 e = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, z, 0u);
         if (a <= a1) {
             const uint64_t lo = (uint64_t)a << sh, hi = (uint64_t)(a + 1) << sh;
             uint32_t below = 0, inside = 0;
@@ -1256,17 +1470,150 @@ __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict
                 below += (uint64_t)es[i] < lo;
                 inside += ((uint64_t)es[i] >= lo) && ((uint64_t)es[i] < hi);
             }
-            e.x = inside ? es[below] : 0xFFFFFFFFu;
-            e.y = (inside >= 2) ? (below | (inside << 16)) : below;
-            if (inside >= 2) w.multi = 1u;
+            e.x = inside >= 1 ? es[below] : 0xFFFFFFFFu;
+            e.y = inside >= 2 ? es[below + 1] : 0xFFFFFFFFu;
+            e.z = z + below;
+            e.w = inside >= 3 ? inside : 0u;
+            if (inside >= 3) w.multi = 1u;
         }
         tab[idx] = e;
     }
 }
 
-hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
+// Range sweep set-up.  Every target's key lies in a candidate range of
+// 2^bits bit patterns starting at a_r, with rbase_r keys below it: after
+// plain scan 2 (a_r = 21-bit prefix << SEL_B3, rbase = keys below the
+// prefix) or after window scan 1 (a_r = fine-bin start, rbase = keys below
+// the fine bin; a series with a target outside its window is left out).
+// Distinct ranges are sorted, adjacent ones merge into groups, and the
+// group boundaries (first value - 1, last value) form the rank table; the
+// fine counters of the ranges are cleared.
+__global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict__ sds,
+                                                    SeriesWork* __restrict__ works, uint2* __restrict__ rtab,
+                                                    uint64_t* __restrict__ fineK, uint64_t* __restrict__ fineL,
+                                                    uint32_t fine_stride, uint32_t window)
 {
-    hipLaunchKernelGGL(k_sweep_prep, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.rtab);
+    __shared__ uint32_t es[RANK_MAX];
+    __shared__ uint32_t sub[RQA_MAX_K];
+    __shared__ uint32_t s_kp, s_z, s_nsub, s_ok, s_shift;
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    const uint32_t bits = window ? w.win_shift : (uint32_t)SEL_B3;
+    if (threadIdx.x == 0) {
+        // series with a NaN or infinite sample end in an error; keep them out
+        uint32_t ok = w.nonfinite ? 0u : 1u;
+        if (window) {
+            ok &= w.win_ok ? 1u : 0u;
+            for (uint32_t r = 0; r < K; ++r) ok &= w.win_hit[r] ? 1u : 0u;
+        }
+        s_ok = ok;
+        w.range_ok = ok;
+        w.range_bits = bits;
+        if (ok) {
+            for (uint32_t r = 0; r < K; ++r) {
+                sub[r] = window ? w.win_lo + (w.win_fbin[r] << bits) : (w.prefix[r] << SEL_B3);
+                w.rbase[r] = window ? w.win_base[r] : w.below[r];
+            }
+            const uint32_t ns = sort_unique(sub, K);
+            s_nsub = ns;
+            w.nsub = ns;
+            for (uint32_t j = 0; j < ns; ++j) w.sub_lo[j] = sub[j];
+            for (uint32_t r = 0; r < K; ++r) {
+                const uint32_t a = window ? w.win_lo + (w.win_fbin[r] << bits) : (w.prefix[r] << SEL_B3);
+                w.t_sub[r] = index_of(sub, ns, a);
+            }
+            // groups of adjacent ranges and their boundaries
+            const uint64_t width = 1ull << bits;
+            uint32_t ng = 0, kp = 0;
+            for (uint32_t j = 0; j < ns; ++j) {
+                if (j == 0 || (uint64_t)sub[j] != (uint64_t)sub[j - 1] + width) {
+                    w.g_lo[ng] = sub[j];
+                    w.g_off[ng] = j << bits;
+                    ++ng;
+                }
+            }
+            w.ngroups = ng;
+            w.g_lo[ng] = 0;
+            w.g_off[ng] = 0;
+            for (uint32_t r = 0; r < K; ++r) {
+                const uint32_t j = w.t_sub[r];
+                uint32_t gi = 0;
+                while (gi + 1 < ng && (w.g_off[gi + 1] >> bits) <= j) ++gi;
+                w.t_group[r] = gi;
+            }
+            const uint32_t z = w.g_lo[0] == 0 ? 1u : 0u;
+            for (uint32_t gi = 0; gi < ng; ++gi) {
+                const uint32_t nj = (gi + 1 < ng ? (w.g_off[gi + 1] >> bits) : ns) - (w.g_off[gi] >> bits);
+                if (w.g_lo[gi] > 0) es[kp++] = w.g_lo[gi] - 1;
+                // last value of the group; keys never exceed +inf
+                const uint64_t last = (uint64_t)w.g_lo[gi] + ((uint64_t)nj << bits) - 1;
+                es[kp++] = (uint32_t)(last < 0x7F800000ull ? last : 0x7F800000ull);
+            }
+            s_kp = kp;
+            s_z = z;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    // clear the fine counters of the ranges
+    const uint32_t nfine = s_nsub << bits;
+    uint64_t* fk = fineK + (size_t)s * fine_stride;
+    uint64_t* fl = fineL + (size_t)s * fine_stride;
+    for (uint32_t i = threadIdx.x; i < nfine; i += blockDim.x) {
+        fk[i] = 0;
+        fl[i] = 0;
+    }
+    build_range_table(w, es, s_kp, s_z, (uint4*)(rtab + (size_t)s * RHO_TABLE), &s_shift);
+}
+
+hipError_t launch_range_prep(hipStream_t st, const DevBufs& b, bool window)
+{
+    hipLaunchKernelGGL(k_range_prep, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.rtab, b.fineK, b.fineL,
+                       b.fine_stride, window ? 1u : 0u);
+    return hipGetLastError();
+}
+
+// After the range sweep: per target, the fine counters of its range resolve
+// the last bits of eps (rank k - rbase inside the range); C = rbase + the
+// keys of the range up to eps; D = line values of rank below the target's
+// group (line ranks 0 .. 2 g) + those from the group start up to eps.
+__global__ void __launch_bounds__(256) k_range_scan(const SeriesDesc* __restrict__ sds,
+                                                    SeriesWork* __restrict__ works,
+                                                    const uint64_t* __restrict__ fineK,
+                                                    const uint64_t* __restrict__ fineL, uint32_t fine_stride)
+{
+    const uint32_t s = blockIdx.x;
+    const uint32_t K = sds[s].K;
+    SeriesWork& w = works[s];
+    if (!w.range_ok) return;
+    const uint32_t bits = w.range_bits, width = 1u << bits;
+    const uint64_t* fk = fineK + (size_t)s * fine_stride;
+    const uint64_t* fl = fineL + (size_t)s * fine_stride;
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        const uint32_t j = w.t_sub[r], gi = w.t_group[r];
+        const uint32_t f0 = w.g_off[gi], fj = j << bits;
+        uint64_t cl = 0;
+        for (uint32_t row = 0; row < 2 * gi + 1; ++row) cl += w.hlam[row];
+        for (uint32_t i = f0; i < fj; ++i) cl += fl[i];
+        const uint64_t want = w.k[r] - w.rbase[r];
+        uint64_t run = 0;
+        uint32_t c = 0;
+        for (; c < width; ++c) {
+            if (run + fk[fj + c] >= want) break;
+            run += fk[fj + c];
+        }
+        if (c == width) { c = width - 1; atomicOr(&w.status, 32u); }
+        for (uint32_t i = 0; i <= c; ++i) cl += fl[fj + i];
+        w.eps_bits[r] = w.sub_lo[j] + c;
+        w.count[r] = w.rbase[r] + run + fk[fj + c];
+        w.dcount[r] = cl;
+    }
+}
+
+hipError_t launch_range_scan(hipStream_t st, const DevBufs& b)
+{
+    hipLaunchKernelGGL(k_range_scan, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.fineK, b.fineL, b.fine_stride);
     return hipGetLastError();
 }
 
@@ -1367,19 +1714,16 @@ hipError_t launch_window_from_sample(hipStream_t st, const DevBufs& b, const uin
     return hipGetLastError();
 }
 
-// Window pass 1: count keys (and line values) below the window and
-// histogram the window in WIN_BINS fine bins.
-template <int NORM, int MC, int TC, int LV>
+// Window pass 1: count keys below the window and histogram the window in
+// WIN_BINS fine bins.
+template <int NORM, int MC, int TC>
 struct WinPass1 {
-    uint32_t* bins;       // LDS [WIN_BINS] keys, then [WIN_BINS] line values
+    uint32_t* bins;       // LDS [WIN_BINS]
     uint64_t* gbins;      // global [S][WIN_BINS]
-    uint64_t* gbinsL;
     SeriesWork* works;
     uint32_t lo, span, shift;
     uint32_t below = 0;   // per lane
-    uint32_t belowL = 0;
     bool active = true;
-    static constexpr bool L = LV != LV_NONE;
     __device__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
@@ -1388,21 +1732,17 @@ struct WinPass1 {
         shift = uniform(w.win_shift);
         active = uniform(w.win_ok) != 0;
         below = 0;
-        belowL = 0;
-        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * WIN_BINS; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
         if (!active) return;
-        for (uint32_t i = threadIdx.x; i < (L ? 2 : 1) * WIN_BINS; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) {
             const uint32_t v = bins[i];
-            uint64_t* dst = i < WIN_BINS ? &gbins[(size_t)s * WIN_BINS + i] : &gbinsL[(size_t)s * WIN_BINS + i - WIN_BINS];
-            if (v) atomicAdd((unsigned long long*)dst, (unsigned long long)v);
+            if (v) atomicAdd((unsigned long long*)&gbins[(size_t)s * WIN_BINS + i], (unsigned long long)v);
         }
         if (below) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)below);
-        if (belowL) atomicAdd((unsigned long long*)&works[s].win_belowL, (unsigned long long)belowL);
         below = 0;
-        belowL = 0;
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
     __device__ __forceinline__ void count(uint32_t u, uint32_t)
@@ -1411,31 +1751,23 @@ struct WinPass1 {
         below += u < lo ? 1u : 0u;
         if (rel <= span) atomicAdd(&bins[rel >> shift], 1u);
     }
-    __device__ __forceinline__ void countL(uint32_t v, uint32_t)
-    {
-        const uint32_t rel = v - lo;
-        belowL += v < lo ? 1u : 0u;
-        if (rel <= span) atomicAdd(&bins[WIN_BINS + (rel >> shift)], 1u);
-    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-// Window pass 2: keys (line values) in a target's fine bin add to that bin's
-// 2^shift sub-bins in global memory (few qualify).
-template <int NORM, int MC, int TC, int LV>
+// Window pass 2: keys in a target's fine bin add to that bin's 2^shift
+// sub-bins in global memory (few keys qualify).
+template <int NORM, int MC, int TC>
 struct WinPass2 {
     uint8_t* table;       // LDS [WIN_BINS] fine bin -> slot
     const uint8_t* gtable;
     uint64_t* fine;       // global [S][K][1 << WIN_MAX_SHIFT]
-    uint64_t* fineL;
     SeriesWork* works;
     uint32_t K;
     uint32_t lo, span, shift;
     unsigned long long* dst;
-    unsigned long long* dstL;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
@@ -1446,7 +1778,6 @@ struct WinPass2 {
         active = uniform(w.win_ok) != 0 && uniform(w.win_nslots) != 0;
         for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) table[i] = gtable[(size_t)s * WIN_BINS + i];
         dst = (unsigned long long*)(fine + (size_t)s * K * (1u << WIN_MAX_SHIFT));
-        dstL = LV != LV_NONE ? (unsigned long long*)(fineL + (size_t)s * K * (1u << WIN_MAX_SHIFT)) : nullptr;
     }
     __device__ void flush(uint32_t) {}
     __device__ __forceinline__ uint32_t look(uint32_t u) const
@@ -1461,121 +1792,79 @@ struct WinPass2 {
         const uint32_t sub = (u - lo) & ((1u << shift) - 1u);
         wave_add(dst, sl * (1u << WIN_MAX_SHIFT) + sub, sl != NO_SLOT);
     }
-    __device__ __forceinline__ void countL(uint32_t v, uint32_t sl) const
-    {
-        const uint32_t sub = (v - lo) & ((1u << shift) - 1u);
-        wave_add(dstL, sl * (1u << WIN_MAX_SHIFT) + sub, sl != NO_SLOT);
-    }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC, LV>(sd, tile_id, lane, *this);
+        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
 
-__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass, bool lines)
-{
-    return (pass == 1 ? (lines ? 2 : 1) * WIN_BINS * 4 : WIN_BINS) + 16;
-}
+__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass) { return (pass == 1 ? WIN_BINS * 4 : WIN_BINS) + 16; }
 
-size_t window_lds_bytes(int pass, bool lines) { return window_lds_bytes_dev(pass, lines); }
+size_t window_lds_bytes(int pass) { return window_lds_bytes_dev(pass); }
 
-template <int PASS, int NORM, int MC, int TC, int LV>
+template <int PASS, int NORM, int MC, int TC>
 __global__ void __launch_bounds__(1024)
 k_window(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
-         uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, WinBufs wb, uint32_t K)
+         uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, uint64_t* __restrict__ bins,
+         const uint8_t* __restrict__ table, uint64_t* __restrict__ fine, uint32_t K)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* slot = (uint32_t*)(smem + window_lds_bytes_dev(PASS, LV != LV_NONE) - 16);
+    uint32_t* slot = (uint32_t*)(smem + window_lds_bytes_dev(PASS) - 16);
     if constexpr (PASS == 1) {
-        WinPass1<NORM, MC, TC, LV> body;
+        WinPass1<NORM, MC, TC> body;
         body.bins = (uint32_t*)smem;
-        body.gbins = wb.bins;
-        body.gbinsL = wb.binsL;
+        body.gbins = bins;
         body.works = works;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else {
-        WinPass2<NORM, MC, TC, LV> body;
+        WinPass2<NORM, MC, TC> body;
         body.table = (uint8_t*)smem;
-        body.gtable = wb.table;
-        body.fine = wb.fine;
-        body.fineL = wb.fineL;
+        body.gtable = table;
+        body.fine = fine;
         body.works = works;
         body.K = K;
         body.dst = nullptr;
-        body.dstL = nullptr;
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     }
 }
 
-using WinFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, WinBufs, uint32_t);
+using WinFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, uint64_t*,
+                       const uint8_t*, uint64_t*, uint32_t);
 
-template <int PASS, int NORM, int LV>
+template <int PASS, int NORM>
 static WinFn window_fn_n(int mclass)
 {
-    if constexpr (LV == LV_ANY) {
-        return k_window<PASS, NORM, 0, 0, LV>;
-    } else {
-        switch (mclass) {
-        case 1: return k_window<PASS, NORM, 1, 0, LV>;
-        case 2: return k_window<PASS, NORM, 3, 3, LV>;
-        case 3: return k_window<PASS, NORM, 3, 5, LV>;
-        default: return k_window<PASS, NORM, 0, 0, LV>;
-        }
+    switch (mclass) {
+    case 1: return k_window<PASS, NORM, 1, 0>;
+    case 2: return k_window<PASS, NORM, 3, 3>;
+    case 3: return k_window<PASS, NORM, 3, 5>;
+    default: return k_window<PASS, NORM, 0, 0>;
     }
 }
 
-template <int PASS, int LV>
-static WinFn window_fn_lv(int v)
+static WinFn window_fn(int pass, int variant)
 {
-    const int norm = v / NUM_MCLASS, mc = v % NUM_MCLASS;
-    return norm == RQA_NORM_MAX ? window_fn_n<PASS, RQA_NORM_MAX, LV>(mc) : window_fn_n<PASS, RQA_NORM_EUCLIDEAN, LV>(mc);
+    const int norm = variant / NUM_MCLASS, mc = variant % NUM_MCLASS;
+    if (pass == 1)
+        return norm == RQA_NORM_MAX ? window_fn_n<1, RQA_NORM_MAX>(mc) : window_fn_n<1, RQA_NORM_EUCLIDEAN>(mc);
+    return norm == RQA_NORM_MAX ? window_fn_n<2, RQA_NORM_MAX>(mc) : window_fn_n<2, RQA_NORM_EUCLIDEAN>(mc);
 }
-
-template <int PASS>
-static WinFn window_fn_p(int variant)
-{
-    const int lv = variant / NUM_SELECT_VARIANTS, v = variant % NUM_SELECT_VARIANTS;
-    if (lv == LV_2) return window_fn_lv<PASS, LV_2>(v);
-    if (lv == LV_ANY) return window_fn_lv<PASS, LV_ANY>(v);
-    return window_fn_lv<PASS, LV_NONE>(v);
-}
-
-static WinFn window_fn(int pass, int variant) { return pass == 1 ? window_fn_p<1>(variant) : window_fn_p<2>(variant); }
 
 hipError_t launch_window_pass(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass, int variant, uint32_t grid,
                               uint32_t block, uint32_t ticket)
 {
-    const bool lines = variant >= NUM_SELECT_VARIANTS;
-    hipLaunchKernelGGL(window_fn(pass, variant), dim3(grid), dim3(block), window_lds_bytes(pass, lines), st, b.sd,
-                       b.S, b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, w, b.K);
+    hipLaunchKernelGGL(window_fn(pass, variant), dim3(grid), dim3(block), window_lds_bytes(pass), st, b.sd, b.S,
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, w.bins, w.table, w.fine, b.K);
     return hipGetLastError();
 }
 
 int window_blocks_per_cu(int pass, int variant, uint32_t block)
 {
     int n = 0;
-    const bool lines = variant >= NUM_SELECT_VARIANTS;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, window_fn(pass, variant), (int)block,
-                                                     window_lds_bytes(pass, lines)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, window_fn(pass, variant), (int)block, window_lds_bytes(pass)) !=
+        hipSuccess)
         return 1;
     return n > 0 ? n : 1;
-}
-
-// Sum of c[0..n) over the block; every thread gets it.  part: LDS
-// [blockDim.x], blockDim.x a power of two.  All threads must call it.
-__device__ uint64_t block_sum(const uint64_t* __restrict__ c, uint32_t n, uint64_t* part)
-{
-    uint64_t v = 0;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += c[i];
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-        __syncthreads();
-    }
-    const uint64_t r = part[0];
-    __syncthreads();
-    return r;
 }
 
 // Block-cooperative search over n counts: the first index whose inclusive
@@ -1617,11 +1906,9 @@ __device__ bool block_find(const uint64_t* __restrict__ c, uint32_t n, uint64_t 
 // After window pass 1: per target, hit if its rank falls inside the window;
 // its fine bin and the count below that bin; pass-2 slots and table.
 __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                                      WinBufs wb, uint32_t lines)
+                                                      const uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
+                                                      uint64_t* __restrict__ fine, uint32_t clear_fine)
 {
-    const uint64_t* __restrict__ bins = wb.bins;
-    uint8_t* __restrict__ table = wb.table;
-    uint64_t* __restrict__ fine = wb.fine;
     __shared__ uint64_t part[257];
     __shared__ uint32_t s_idx;
     __shared__ uint64_t s_before;
@@ -1664,20 +1951,10 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
     __syncthreads();
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) tb[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.win_nslots = nu;
-    // line values below each hit target's fine bin
-    if (lines) {
-        const uint64_t* cl = wb.binsL + (size_t)s * WIN_BINS;
-        const uint64_t belowL = w.win_belowL;
-        for (uint32_t r = 0; r < K; ++r) {
-            if (!w.win_hit[r]) continue;
-            const uint64_t v = block_sum(cl, w.win_fbin[r], part);
-            if (threadIdx.x == 0) w.win_baseL[r] = belowL + v;
-        }
-    }
-    // clear the sub-bins pass 2 will count into
-    const uint32_t nsub = 1u << w.win_shift;
-    for (int part_ = 0; part_ < (lines ? 2 : 1); ++part_) {
-        uint64_t* f = (part_ ? wb.fineL : fine) + (size_t)s * K * (1u << WIN_MAX_SHIFT);
+    // clear the sub-bins window pass 2 will count into
+    if (clear_fine) {
+        const uint32_t nsub = 1u << w.win_shift;
+        uint64_t* f = fine + (size_t)s * K * (1u << WIN_MAX_SHIFT);
         for (uint32_t u = 0; u < nu; ++u)
             for (uint32_t i = threadIdx.x; i < nsub; i += blockDim.x) f[(size_t)u * (1u << WIN_MAX_SHIFT) + i] = 0;
     }
@@ -1686,9 +1963,8 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
 // After window pass 2: the sub-bin of each hit target gives its threshold;
 // count = #{key <= eps}.
 __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                                      WinBufs wb, uint32_t lines)
+                                                      const uint64_t* __restrict__ fine)
 {
-    const uint64_t* __restrict__ fine = wb.fine;
     __shared__ uint64_t part[257];
     __shared__ uint32_t s_idx;
     __shared__ uint64_t s_before;
@@ -1700,14 +1976,10 @@ __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restri
         if (!w.win_hit[r]) continue;
         const uint64_t* c = fine + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT);
         const bool ok = block_find(c, nsub, w.k[r] - w.win_base[r], &s_idx, &s_before, part);
-        uint64_t inL = 0;
-        if (ok && lines)
-            inL = block_sum(wb.fineL + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT), s_idx + 1, part);
         if (threadIdx.x == 0) {
             if (ok) {
                 w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + s_idx;
                 w.count[r] = w.win_base[r] + s_before + c[s_idx];
-                if (lines) w.dcount[r] = w.win_baseL[r] + inL;
             } else {
                 w.win_hit[r] = 0u;
                 atomicOr(&w.status, 8u);
@@ -1719,8 +1991,12 @@ __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restri
 
 hipError_t launch_window_scan(hipStream_t st, const DevBufs& b, const WinBufs& w, int pass)
 {
-    if (pass == 1) hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w, b.lines);
-    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w, b.lines);
+    // scan 1 clears the fine counters of window pass 2 unless the range sweep
+    // (which clears its own) follows
+    if (pass == 1)
+        hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.bins, w.table, w.fine,
+                           w.fine ? 1u : 0u);
+    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.fine);
     return hipGetLastError();
 }
 
@@ -1808,27 +2084,16 @@ hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint
 hipError_t set_kernel_lds_limits(size_t max_dyn_lds)
 {
     hipError_t err = hipSuccess;
-    // selection and window kernels: plain, lmin = 2 and any-lmin line classes
-    for (int lv = 0; lv < 3; ++lv) {
-        for (int v0 = 0; v0 < NUM_SELECT_VARIANTS; ++v0) {
-            const int v = lv * NUM_SELECT_VARIANTS + v0;
-            for (int p = 1; p <= 3; ++p) {
-                hipError_t e = hipFuncSetAttribute((const void*)select_fn_pass(p, v),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
-                if (e != hipSuccess) err = e;
-            }
-            for (int p = 1; p <= 2; ++p) {
-                hipError_t e = hipFuncSetAttribute((const void*)window_fn(p, v),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
-                if (e != hipSuccess) err = e;
-            }
-        }
-    }
+    auto set = [&](const void* f) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
+        if (e != hipSuccess) err = e;
+    };
     for (int v = 0; v < NUM_SELECT_VARIANTS; ++v) {
+        for (int p = 1; p <= 3; ++p) set((const void*)select_fn_pass(p, v));
+        for (int p = 1; p <= 2; ++p) set((const void*)window_fn(p, v));
         for (int l = 0; l < 3; ++l) {
-            hipError_t e = hipFuncSetAttribute((const void*)sweep_fn(v * 3 + l),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn_lds);
-            if (e != hipSuccess) err = e;
+            set((const void*)sweep_fn(v * 3 + l));
+            set((const void*)range_fn(v * 3 + l));
         }
     }
     return err;

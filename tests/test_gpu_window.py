@@ -125,3 +125,19 @@ def test_window_lines_match_plain_and_sweep(ctx, lmin, m, tau, norm):
             assert st["series_fallback"] == 0 and st["full_passes"] == 2
     dc = ctx.det_curve(dev(y), p, plain["eps"])
     assert np.array_equal(dc["count"], plain["count"]) and np.array_equal(dc["det"], plain["det"])
+
+
+def test_nonfinite_series_rejected_in_every_selection_mode(ctx):
+    from paper_2208_09136_amd.rqa import RqaError
+    c = CASES[0]
+    bad = c["y"].copy()
+    bad[321] = np.nan
+    ctx.set_window(0.0, 1.0)
+    for flags in (0, SAMPLE, WINDOW):
+        print(f"[window-nan] flags={flags}", flush=True)
+        with pytest.raises(RqaError) as e:
+            ctx.run(dev(bad), prm(c), c["rr"], flags=flags)
+        assert e.value.name == "RQA_ERR_NONFINITE"
+    # the context still works afterwards
+    got = ctx.run(dev(c["y"]), prm(c), c["rr"], flags=SAMPLE)
+    assert np.array_equal(got["eps"], ctx.run(dev(c["y"]), prm(c), c["rr"])["eps"])
