@@ -33,8 +33,9 @@ import synth  # noqa: E402
 
 METRIC = "recurrence cells x thresholds/s at N=1e5, K=20 (+ batched series/s), % VALU peak"
 K = 20
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, in lane-ops/s.
-VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# VALU peak of MI355X in lane-ops/s: the FP32 vector peak of 157.3 TFLOP/s
+# counts an FMA as two, i.e. 256 CUs x 128 lanes x 2.4 GHz one-op lane slots.
+VALU_PEAK = 157.3e12 / 2
 # Algorithmic VALU lane-ops of one key for (norm, m): the m subtractions, the
 # m |.| or squares and the m-1 max or add steps.
 def key_ops(norm, m):
@@ -148,15 +149,15 @@ def main():
     ph = dict(zip(rqa.PHASES, (phases / args.steps).tolist()))
 
     # roofline of the dominant kernel: the phase with the largest device time;
-    # one launch per phase per step.  Algorithmic lane-ops per pair: the key,
-    # then per selection pass 2 (bucket of the key, one count), per sweep 2 per
-    # threshold (one comparison, one run-length update).
+    # one launch per phase per step.  Algorithmic lane-ops per pair: the key
+    # (3m - 1), then per counting pass 6 (bucket, table lookup, count) and for
+    # the line sweep 2 per threshold (one comparison, one run-length update)
+    # plus the 6 of the last radix pass it takes over.
     kops = key_ops(1, 3)
     per_launch_ops = {
-        "select_pass1": sum(cells) * (kops + 2),
-        "select_pass2": sum(cells) * (kops + 2),
-        "select_pass3": sum(cells) * (kops + 2),
-        "sweep": sum(cells) * (kops + 2 * K),
+        "select_pass1": sum(cells) * (kops + 6),
+        "select_pass2": sum(cells) * (kops + 6),
+        "sweep": sum(cells) * (kops + 6 + 2 * K),
     }
     dom = max(per_launch_ops, key=lambda p: ph[p])
     achieved = per_launch_ops[dom] / (ph[dom] * 1e-3)
@@ -177,19 +178,45 @@ def main():
             roofline["valu_lane_ops_measured"] = kc["valu_insts"] * 64
             roofline["valu_busy_frac"] = kc["valu_insts"] * 64 / (ph[dom] * 1e-3) / VALU_PEAK
 
+    # the same step with windowed selection (sketch-sample window, and the
+    # trained network's window when present): identical results, fewer passes
+    windows = {}
+    from paper_2208_09136_amd import bracket
+    have_net = not args.no_bracket and os.path.exists(args.bracket_file)
+    if have_net:
+        bracket.load(ctx, args.bracket_file)
+    for name, flags in (("sample", rqa.RQA_SEL_SAMPLE), ("network", rqa.RQA_SEL_LEARNED)):
+        if name == "network" and not have_net:
+            continue
+        got = ctx.batch(concat, offs, prm, rr, flags=flags)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            got = ctx.batch(concat, offs, prm, rr, flags=flags)
+        torch.cuda.synchronize()
+        wsec = (time.perf_counter() - t0) / args.steps
+        st = ctx.selection_stats()
+        wph = ctx.phase_times()
+        windows[name] = {"ms_per_step": wsec * 1e3, "value": cell_thr / wsec, "full_passes": st["full_passes"],
+                         "phases_ms": wph,
+                         "series_fallback": st["series_fallback"],
+                         "identical": bool(all(np.array_equal(got[k], out[k]) for k in ("eps", "count", "det"))),
+                         "speedup_vs_plain": sec / wsec}
+
     result = {
         "metric": METRIC, "value": value, "unit": "cell-thresholds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "2 series x N=1e5 (Lorenz-x 0 dB, logistic r=4 -10 dB), m=3, tau=5, "
-                               "Euclidean, Theiler 1, l_min 2, K=20 RR 0.01..0.20; select + sweep",
+                               "Euclidean, Theiler 1, l_min 2, K=20 RR 0.01..0.20; exact selection + DET",
                    "pairs_per_series": cells, "K": K, "global_batch": len(cases), "seq_len": 100_000,
                    "parallelism": "single-gpu"},
         "phases_ms": ph,
         "autotune": {"chunk_tiles": tuned_chunk, "seconds": t_tune},
         "valu_peak_frac": step_ops / sec / VALU_PEAK,
         "roofline": roofline,
+        "windowed_selection": windows,
         "det_mean": out["det_mean"].tolist(),
     }
 

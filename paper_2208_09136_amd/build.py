@@ -27,15 +27,17 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, defines=()):
+    """Compile librqa.so (or `out`); `defines` are extra -D options."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + ["-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

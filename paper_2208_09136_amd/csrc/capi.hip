@@ -349,14 +349,29 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const uint64_t ntiles = (uint64_t)d.Smax * d.B - (uint64_t)d.q * ((uint64_t)d.Smax * (d.Smax - 1) / 2);
         if (ntiles >= (1ull << 31)) return fail(RQA_ERR_UNSUPPORTED, "too many tiles; raise the segment length");
         d.ntiles = (uint32_t)ntiles;
-        d.nchunks = (uint32_t)((ntiles + CT - 1) / CT);
-        d.chunk_begin = g.nchunks;  // chunk numbering restarts in every group
         d.variant = (uint32_t)swp_var[s];
         d.seed = job.seed + s;
         d.f_logn = (float)(std::log2((double)z.n) / 16.0);
         d.f_m = (float)((double)z.p.m / 4.0);
-        g.nchunks += d.nchunks;
         maxn = std::max<uint32_t>(maxn, (uint32_t)z.n);
+    }
+    // The window pass flushes WIN_BINS fine bins (nearly all non-zero) each
+    // time a workgroup moves to another series: give windowed jobs chunks
+    // large enough that a workgroup sees about eight of them in all.
+    if ((job.mode & MODE_SELECT) && job.sel != 0) {
+        uint64_t tiles = 0;
+        for (uint32_t i = 0; i < S; ++i) tiles += sd[i].ntiles;
+        const uint64_t wgs = (uint64_t)c->num_cu * 2;
+        const uint64_t want = tiles / (wgs * 8);
+        CT = (uint32_t)std::max<uint64_t>(CT, std::min<uint64_t>(want, 1024));
+    }
+    for (Group& g : groups) {
+        for (uint32_t i = g.begin; i < g.end; ++i) {
+            SeriesDesc& d = sd[i];
+            d.nchunks = (d.ntiles + CT - 1) / CT;
+            d.chunk_begin = g.nchunks;  // chunk numbering restarts in every group
+            g.nchunks += d.nchunks;
+        }
     }
 
     // device layout
@@ -385,6 +400,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_fineL = fused ? carve(sizeof(uint64_t) * S * fine_stride) : 0;
     const size_t o_pred = window ? carve(sizeof(float) * S * MLP_OUT) : 0;
     const size_t o_delta = window ? carve(sizeof(float) * MLP_OUT) : 0;
+    if (window && window_lds_bytes(1) > c->max_lds)
+        return fail(RQA_ERR_UNSUPPORTED, "the window pass needs %zu bytes of LDS per workgroup", window_lds_bytes(1));
     rqa_status st = ensure_pool(c, off);
     if (st) return st;
     char* pool = (char*)c->pool;
@@ -495,7 +512,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                 wv.table = wb.table + (size_t)g.begin * WIN_BINS;
                 wv.fine = fused ? nullptr : wb.fine + (size_t)g.begin * K * (1u << WIN_MAX_SHIFT);
                 const int var = g.sel;
-                const uint32_t block = 512;
+                const uint32_t block = pass == 1 ? WIN_BLOCK : 512;
                 const int per_cu = window_blocks_per_cu(pass, var, block);
                 const uint32_t grid = c->grid ? c->grid
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
@@ -868,7 +885,7 @@ std::vector<uint32_t> segment_candidates(uint64_t L0)
     return v;
 }
 
-const uint32_t CHUNK_CANDIDATES[] = {2, 8, 32};
+const uint32_t CHUNK_CANDIDATES[] = {2, 8, 32, 128, 512};
 
 // Tunes the segment length of each size bucket present in the job (on up to
 // 64 of its series, chunk size at the default) and then the chunk size of the

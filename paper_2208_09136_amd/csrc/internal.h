@@ -120,10 +120,12 @@ struct SeriesWork {
     uint32_t win_nslots;
 };
 
-// Window selection: WIN_BINS fine bins over the window; the last
-// win_shift <= WIN_MAX_SHIFT bits are resolved in a second pass.
-constexpr int WIN_BITS = 14;
-constexpr uint32_t WIN_BINS = 1u << WIN_BITS;
+// Window selection: WIN_BINS fine bins over the window (the whole 160 KB LDS
+// of a CU as 32-bit counters, one workgroup of 1024 threads per CU); the last
+// win_shift <= WIN_MAX_SHIFT bits are resolved by the range sweep or a second
+// window pass.
+constexpr uint32_t WIN_BINS = 39 * 1024;
+constexpr uint32_t WIN_BLOCK = 1024;
 constexpr uint32_t WIN_MAX_SHIFT = 13;
 
 // Device buffers of one call (host-side handle).

@@ -384,10 +384,17 @@ __device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t ti
     }
 }
 
+#ifndef RQA_P1_COPIES
+#define RQA_P1_COPIES 4
+#endif
+// Interleaved copies of the pass-1 histogram: lane L counts into copy L mod
+// P1_COPIES, so lanes of one wave that hit the same bucket hit different words.
+constexpr uint32_t P1_COPIES = RQA_P1_COPIES;
+
 // Bytes of a selection pass's LDS tables and bins; the work-queue word follows.
 __host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G)
 {
-    if (pass == 1) return SEL_N1 * 4;
+    if (pass == 1) return SEL_N1 * 4 * P1_COPIES;
     if (pass == 2) return SEL_N1 * 2 + (size_t)G * SEL_N2 * 4;
     return SEL_N1 + (size_t)K * SEL_N2;
 }
@@ -395,27 +402,31 @@ __host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32
 // Pass 1: histogram of the top SEL_B1 bits of every key.
 template <int NORM, int MC, int TC>
 struct SelPass1 {
-    uint32_t* bins;   // LDS [SEL_N1]
+    uint32_t* bins;   // LDS [SEL_N1][P1_COPIES]
     uint64_t* h1;     // global [S][SEL_N1]
     bool active = true;
+    uint32_t copy = 0;
     __device__ void begin(uint32_t)
     {
-        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < SEL_N1 * P1_COPIES; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
         for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) {
-            const uint32_t v = bins[i];
+            uint32_t v = 0;
+            for (uint32_t c = 0; c < P1_COPIES; ++c) v += bins[i * P1_COPIES + c];
             if (v) atomicAdd((unsigned long long*)&h1[(size_t)s * SEL_N1 + i], (unsigned long long)v);
         }
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
     __device__ __forceinline__ void count(uint32_t u, uint32_t) const
     {
-        atomicAdd(&bins[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)], 1u);
+        if constexpr (P1_COPIES == 1) atomicAdd(&bins[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)], 1u);
+        else atomicAdd(&bins[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1) * P1_COPIES + copy], 1u);
     }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
+        copy = (uint32_t)lane & (P1_COPIES - 1);
         select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
@@ -708,7 +719,7 @@ __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sd
 // After pass 2: resolve SEL_B2 more bits per target, assign pass-3 slots,
 // fill T2 (per pass-2 slot and sub-bucket).
 __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2)
+                                               uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2all)
 {
     __shared__ uint32_t uniq[RQA_MAX_K];
     __shared__ uint32_t nuniq;
@@ -717,9 +728,10 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
     SeriesWork& w = works[s];
     uint8_t* t2 = T2 + (size_t)s * K * SEL_N2;
     const uint32_t n2 = w.nslots2;
+    const uint64_t* h2 = h2all + (size_t)s * K * SEL_N2;
     for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) t2[i] = NO_SLOT;
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
-        const uint64_t* h = h2 + ((size_t)s * K + w.slot[r]) * SEL_N2;
+        const uint64_t* h = h2 + (size_t)w.slot[r] * SEL_N2;
         const uint64_t want = w.k[r] - w.below[r];
         uint64_t run = 0;
         uint32_t c = 0;
@@ -1741,7 +1753,10 @@ struct WinPass1 {
             const uint32_t v = bins[i];
             if (v) atomicAdd((unsigned long long*)&gbins[(size_t)s * WIN_BINS + i], (unsigned long long)v);
         }
-        if (below) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)below);
+        // one atomic per wave on the series' single counter (not one per lane)
+        uint32_t b = below;
+        for (int off = 32; off > 0; off >>= 1) b += __shfl_xor(b, off);
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)b);
         below = 0;
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
@@ -1906,7 +1921,7 @@ __device__ bool block_find(const uint64_t* __restrict__ c, uint32_t n, uint64_t 
 // After window pass 1: per target, hit if its rank falls inside the window;
 // its fine bin and the count below that bin; pass-2 slots and table.
 __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                                      const uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
+                                                      uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
                                                       uint64_t* __restrict__ fine, uint32_t clear_fine)
 {
     __shared__ uint64_t part[257];
