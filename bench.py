@@ -2,19 +2,23 @@
 """Benchmark of the averaged-RQA hot path on one MI355X.
 
 A step is one whole pass of the path over the large workload: exact
-threshold selection for K = 20 target recurrence rates (three radix passes)
-and the line sweep giving RR, DET and the averaged DET, for both large series
-(Lorenz-x + 0 dB noise and logistic r=4 + -10 dB noise, N = 10^5, m = 3,
-tau = 5, Euclidean norm, Theiler window 1, l_min = 2), as one rqa_batch call.
+threshold selection for K = 20 target recurrence rates (two radix counting
+passes, the last bits resolved by the line sweep) and the line sweep giving
+RR, DET and the averaged DET, for both large series (Lorenz-x + 0 dB noise
+and logistic r=4 + -10 dB noise, N = 10^5, m = 3, tau = 5, Euclidean norm,
+Theiler window 1, l_min = 2), as one rqa_batch call with plain selection.
 Inputs are resident in device memory before the timed region.
 
 value = pairs x thresholds per second over the timed steps, where pairs are
 the M = (Nv-1) Nv / 2 upper-triangle pairs each series has.
 
-Also reported (outside the timed steps): the 600-series batched ensemble
-(series/s, batched against one call per series), per-phase device times from
-HIP events on the library's stream, the roofline of the dominant kernel and
-the CPU oracle timed on a bounded sample.
+Also reported (outside the timed steps): the same step with the sketch
+window and the trained network's window, the 600-series batched ensemble
+(series/s, batched against one call per series), the network on 200
+held-out series, per-phase device times from HIP events on the library's
+stream, the roofline of the dominant kernel (with counter-derived traffic
+and VALU rate when the stored counters match the sources) and the CPU
+oracle timed on a bounded sample.
 
 Prints one JSON line.
 """
