@@ -245,6 +245,14 @@ rqa_status rqa_tune_load(rqa_ctx *ctx, const char *path);
  * work queue empty and exit.  Applies to later calls on this context. */
 rqa_status rqa_set_grid(rqa_ctx *ctx, uint32_t workgroups);
 
+/* The averaged-DET curve over an ordered RR set (averaged-determinism
+ * equation of the Averaged RQA section, with RR* running over the set):
+ * curve_out[r] = (DET_0 + ... + DET_r) / (r + 1), summed left to right in
+ * double, for r = 0..K-1 (curve_out[K-1] equals the mean DET of rqa_run).  A
+ * NaN DET (empty plot) makes the rest of the curve NaN.  Host arrays; no
+ * device work.  Returns RQA_ERR_INVALID_ARG for NULL pointers or K = 0. */
+rqa_status rqa_averaged_det(const double *det, uint32_t K, double *curve_out);
+
 /* Human-readable name of a status code (static string). */
 const char *rqa_status_string(rqa_status s);
 

@@ -1270,6 +1270,17 @@ rqa_status rqa_tune_load(rqa_ctx* c, const char* path)
     return RQA_OK;
 }
 
+rqa_status rqa_averaged_det(const double* det, uint32_t K, double* curve_out)
+{
+    if (!det || !curve_out || K == 0) return fail(RQA_ERR_INVALID_ARG, "det or curve_out is NULL, or K is 0");
+    double sum = 0.0;
+    for (uint32_t r = 0; r < K; ++r) {
+        sum += det[r];
+        curve_out[r] = sum / (double)(r + 1);
+    }
+    return RQA_OK;
+}
+
 const char* rqa_status_string(rqa_status s)
 {
     switch (s) {

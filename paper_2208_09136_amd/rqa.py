@@ -73,6 +73,7 @@ SIGNATURES = {
     "rqa_set_window": (_i32, [_vp, ctypes.c_float, ctypes.c_float]),
     "rqa_set_sample_width": (_i32, [_vp, ctypes.c_float]),
     "rqa_selection_stats": (_i32, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    "rqa_averaged_det": (_i32, [_dp, _u32, _dp]),
     "rqa_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_tune_load": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_status_string": (ctypes.c_char_p, [_i32]),
@@ -282,6 +283,15 @@ def rqa_selection_stats(ctx):
     a, b, c = _u32(0), _u32(0), _u32(0)
     _check(load().rqa_selection_stats(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return {"full_passes": a.value, "series_fallback": b.value, "targets_missed": c.value}
+
+
+def rqa_averaged_det(det):
+    """Averaged-DET curve over an ordered RR set: element r is the mean of
+    det[0..r] (left fold in double, in the library)."""
+    d = _a(det, np.float64)
+    out = np.zeros(d.size, np.float64)
+    _check(load().rqa_averaged_det(_p(d, ctypes.c_double), d.size, _p(out, ctypes.c_double)))
+    return out
 
 
 def rqa_tune_save(ctx, path):

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2208_09136_amd import rqa
@@ -50,3 +51,21 @@ def test_series_must_be_device_memory():
     import numpy as np
     with pytest.raises(TypeError):
         rqa._series_ptr(np.zeros(10, np.float32))
+
+
+def test_averaged_det_curve_host_function():
+    # host-only entry point: cumulative means of an ordered DET curve
+    from paper_2208_09136_amd import rqa
+    got = rqa.rqa_averaged_det([0.5, 1.0, 0.0, 0.25])
+    assert np.array_equal(got, [0.5, 0.75, 0.5, 0.4375])
+    dets = np.random.default_rng(1).uniform(size=99)
+    want = np.empty(99)
+    s = 0.0
+    for r, d in enumerate(dets):     # the definition, summed left to right
+        s += d
+        want[r] = s / (r + 1)
+    assert np.array_equal(rqa.rqa_averaged_det(dets), want)
+    nan = rqa.rqa_averaged_det([0.5, float("nan"), 1.0])
+    assert nan[0] == 0.5 and np.isnan(nan[1]) and np.isnan(nan[2])
+    with pytest.raises(rqa.RqaError):
+        rqa.rqa_averaged_det([])

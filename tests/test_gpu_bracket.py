@@ -70,3 +70,18 @@ def test_untrained_network_falls_back_and_stays_exact(ctx, trained):
     finally:
         ctx.mlp_set_params(theta)
         ctx.mlp_set_bracket(trained[2])
+
+
+def test_committed_network_saves_a_pass_on_held_out_series(ctx):
+    # the shipped parameters (trained on 50,000 seeded series) bracket every
+    # target of fresh held-out series: two passes, results identical to plain
+    import os
+    path = os.path.join(os.path.dirname(bracket.__file__), "bracket_params.npz")
+    meta = bracket.load(ctx, path)
+    assert meta["train"] == 50000
+    te = _set(40, 907, 20000, 20000, m=3)
+    ev = bracket.evaluate(ctx, *te, repeats=1)
+    print(ev, flush=True)
+    assert ev["network"]["exact"]
+    assert ev["network"]["miss_rate"] <= 0.05
+    assert ev["network"]["passes_per_series"] <= 2.15

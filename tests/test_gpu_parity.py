@@ -347,3 +347,29 @@ def test_selection_lines_equal_sweep(ctx, m, tau, norm, w, lmin):
     assert np.array_equal(dc["count"], got["count"])
     assert np.array_equal(dc["det"], got["det"], equal_nan=True)
     assert dc["det_mean"] == got["det_mean"] or (np.isnan(dc["det_mean"]) and np.isnan(got["det_mean"]))
+
+
+# ---------------------------------------------------------------- paper-scale RR set
+RR_99 = np.array([k / 100.0 for k in range(1, 100)])
+
+
+@pytest.mark.parametrize("system,m,tau,norm", [("logistic", 1, 1, 0), ("lorenz", 3, 5, 1), ("sine", 1, 1, 1)])
+def test_paper_rr_set_k99(ctx, system, m, tau, norm):
+    # the paper's RR set 1..99 %: exact thresholds, RR and DET for all 99
+    # targets equal the oracle, and the averaged-DET curve over RR* equals the
+    # running means of the oracle's DET values
+    y = synth.series(system, 3000, 0.0, (10, m, tau, norm))
+    case = {"name": f"k99_{system}", "y": y, "m": m, "tau": tau, "norm": norm, "theiler": 1, "lmin": 2,
+            "rr": RR_99}
+    got = check_case(ctx, case)
+    want = oracle_run(case)
+    from paper_2208_09136_amd import rqa
+    curve = rqa.rqa_averaged_det(got["det"])
+    s, ref = 0.0, []
+    for r, d in enumerate(want["det"]):
+        s += d
+        ref.append(s / (r + 1))
+    assert np.array_equal(curve, np.array(ref))
+    assert curve[-1] == got["det_mean"]
+    win = ctx.run(dev(y), prm(case), RR_99, flags=4)
+    assert np.array_equal(win["eps"], got["eps"]) and np.array_equal(win["det"], got["det"])
