@@ -47,6 +47,8 @@ extern "C" {
 #endif
 
 #define RQA_MAX_K 128
+#define RQA_MAX_HIST_K 32          /* distinct thresholds of one full-histogram call */
+#define RQA_MAX_HIST_LEN (1u << 24) /* entries per full-histogram row */
 
 typedef struct rqa_ctx rqa_ctx;
 
@@ -78,7 +80,7 @@ enum {
     RQA_SEL_PLAIN = 0,   /* exact selection: three radix passes over all pairs */
     RQA_SEL_LEARNED = 1, /* exact selection inside a key window the network predicts (two passes);
                             series with a target outside the window fall back to RQA_SEL_PLAIN */
-    RQA_FULL_HIST = 2,   /* reserved for the full line-length histogram: RQA_ERR_UNSUPPORTED */
+    RQA_FULL_HIST = 2,   /* rqa_det_curve only: also return the full line-length histogram P(l) */
     RQA_SEL_SAMPLE = 4,  /* as RQA_SEL_LEARNED with the window from sketch-sample quantiles (no network) */
     RQA_SEL_WINDOW = 8   /* as RQA_SEL_LEARNED with the window set by rqa_set_window (for tests) */
 };
@@ -111,8 +113,20 @@ rqa_status rqa_select_thresholds(rqa_ctx *ctx, const float *series_dev, uint64_t
  *   eps: K thresholds in key units, each >= 0 or +inf, not NaN (host).
  *   count_out[K]: C_r = #{key <= eps_r};  rr_out[K]: C_r / M;
  *   det_out[K]: DET_r (NaN when C_r = 0);  det_mean_out[1]: mean of det_out.
- *   hist_out/hist_len: must be NULL/0 (the full histogram is not built yet).
- * flags: 0. */
+ * flags: 0, or RQA_FULL_HIST for the diagonal line-length histogram P_r(l)
+ * behind Eq. 4 (one more pass, with whole diagonals per workgroup):
+ *   hist_out[K * hist_len] (host), row r at hist_out + r * hist_len:
+ *     entry l < hist_len - 1 = number of diagonal lines of exactly l
+ *     recurrent pairs (maximal runs of j - i = const with key <= eps_r, every
+ *     line inside the pairs j - i >= theiler); entry hist_len - 1 also takes
+ *     every longer line; entry 0 is 0 (unless hist_len = 1, where it counts
+ *     all lines).  So sum_l l P_r(l) = C_r when hist_len exceeds the longest
+ *     line, and DET_r = sum_{l >= lmin} l P_r(l) / C_r.
+ *   hist_len: 1 .. RQA_MAX_HIST_LEN.  Without the flag hist_out must be NULL
+ *     and hist_len 0.
+ *   Limits of the full histogram: at most RQA_MAX_HIST_K distinct values
+ *   among eps and fewer than 2^24 - 1 embedded vectors, else
+ *   RQA_ERR_UNSUPPORTED. */
 rqa_status rqa_det_curve(rqa_ctx *ctx, const float *series_dev, uint64_t n,
                          const rqa_params *p, const float *eps, uint32_t K, uint32_t flags,
                          uint64_t *count_out, double *rr_out, double *det_out,
@@ -144,7 +158,8 @@ rqa_status rqa_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const ui
  * context stream when timing is enabled (rqa_set_timing) and summed over
  * all launches of the call.  times_out[0..n_out-1] receives: [0] selection
  * pass 1, [1] pass 2, [2] pass 3, [3] sweep, [4] everything else (checks,
- * sketch, network, scans, preparation).  Windowed selection books its two
+ * sketch, network, scans, preparation), [5] full line-length histogram
+ * pass (rqa_det_curve with RQA_FULL_HIST).  Windowed selection books its two
  * passes as passes 1 and 2; a plain fallback adds its three passes to
  * passes 1-3.  Returns the number of entries written. */
 int rqa_phase_times(rqa_ctx *ctx, double *times_out, int n_out);

@@ -43,7 +43,7 @@ rqa_status fail(rqa_status st, const char* fmt, ...)
             return fail(RQA_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
     } while (0)
 
-enum Phase { PH_P1 = 0, PH_P2 = 1, PH_P3 = 2, PH_SWEEP = 3, PH_OTHER = 4, PH_N = 5 };
+enum Phase { PH_P1 = 0, PH_P2 = 1, PH_P3 = 2, PH_SWEEP = 3, PH_OTHER = 4, PH_HIST = 5, PH_N = 6 };
 
 // Size bucket of the autotuner: log2 of the number of vectors, the kernel
 // variant (norm, embedding class, line class) and K up to 32 or beyond.  The
@@ -259,7 +259,10 @@ struct Timer {
 // MODE_FUSED: counting passes, then the range sweep, which resolves the
 // last bits of every threshold and counts C and D at it in one pass.
 // MODE_BOTH: three counting passes, then the sweep at the thresholds found.
-enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3, MODE_SKETCH = 4, MODE_LINES = 8, MODE_FUSED = 9 };
+// MODE_HIST: full line-length histogram at given thresholds (whole-diagonal
+// tiles, after the rank tables of the sweep).
+enum Mode { MODE_SELECT = 1, MODE_SWEEP = 2, MODE_BOTH = 3, MODE_SKETCH = 4, MODE_LINES = 8, MODE_FUSED = 9,
+            MODE_HIST = 16 };
 
 struct Job {
     std::vector<Series> series;
@@ -279,6 +282,9 @@ struct Job {
     std::vector<float> features;     // S*SKETCH_FEATURES (sketch mode)
     std::vector<uint32_t> scale;     // S (sketch mode)
     std::vector<uint8_t> hit;        // S*K, window selection: target resolved in the window
+    uint32_t hist_len = 0;           // histogram mode: entries per row (length 0 .. hist_len-1)
+    uint32_t hist_kp = 0;            // histogram mode: largest number of distinct thresholds
+    std::vector<uint64_t> hist;      // S*K*hist_len, P_r(l), caller order
 };
 
 rqa_status ensure_acts(rqa_ctx* c, uint32_t B, MlpActs& a);
@@ -291,7 +297,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     uint32_t CT;
     {
         const Series& z0 = job.series[0];
-        CT = chunk_for(c, S, z0.n - (uint64_t)(z0.p.m - 1) * z0.p.tau, z0.p, K);
+        CT = (job.mode & MODE_HIST) ? (uint32_t)(HIST_BLOCK_HOST / TILE_W) : chunk_for(c, S, z0.n - (uint64_t)(z0.p.m - 1) * z0.p.tau, z0.p, K);
     }
 
     // descriptors, ordered by kernel variant so each launch sees a contiguous range
@@ -331,7 +337,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
         const uint64_t L0 = nv - z.p.theiler;
         SeriesDesc& d = sd[i];
-        const uint32_t T = segment_for(c, nv, z.p, K);
+        // histogram mode: one segment per diagonal, so no line crosses a tile
+        const uint32_t T = (job.mode & MODE_HIST) ? (uint32_t)((L0 + TILE_W - 1) / TILE_W * TILE_W)
+                                                  : segment_for(c, nv, z.p, K);
         d.y = job.base + z.offset;
         d.n = (uint32_t)z.n;
         d.nv = (uint32_t)nv;
@@ -385,6 +393,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
     const bool window = (job.mode & MODE_SELECT) && job.sel != 0;
     const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
+    const bool hist = (job.mode & MODE_HIST) != 0;
+    const size_t hist_words = hist ? (size_t)S * job.hist_len * (job.hist_kp + 1) : 0;
+    const size_t o_dh = hist ? carve(sizeof(uint64_t) * hist_words) : 0;
     const size_t zero_end = off;  // tickets and histograms are cleared every call
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
@@ -442,7 +453,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const uint32_t s = order[i];
         for (uint32_t r = 0; r < K; ++r) {
             if (job.mode & MODE_SELECT) h_work[i].k[r] = job.k[(size_t)s * K + r];
-            else if (job.mode & MODE_SWEEP) h_work[i].eps_bits[r] = job.eps_bits[(size_t)s * K + r];
+            else if (job.mode & (MODE_SWEEP | MODE_HIST)) h_work[i].eps_bits[r] = job.eps_bits[(size_t)s * K + r];
         }
     }
 
@@ -558,6 +569,23 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             HIP_TRY(tm.end());
         }
     }
+    if (hist) {
+        HIP_TRY(tm.begin(PH_OTHER));
+        HIP_TRY(launch_sweep_prep(sm, all));
+        HIP_TRY(tm.end());
+        HIP_TRY(tm.begin(PH_HIST));
+        for (const Group& g : groups) {
+            DevBufs v = view(g);
+            const int per_cu = hist_blocks_per_cu(g.sel, job.hist_kp);
+            const uint32_t grid = c->grid ? c->grid
+                                          : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
+            const int t = take(1);
+            if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
+            HIP_TRY(launch_hist(sm, v, g.sel, grid, (uint64_t*)(pool + o_dh) + (size_t)g.begin * job.hist_len * (job.hist_kp + 1),
+                                job.hist_len, job.hist_kp, (uint32_t)t));
+        }
+        HIP_TRY(tm.end());
+    }
     if ((job.mode & MODE_SWEEP) || fused) {
         HIP_TRY(tm.begin(PH_OTHER));
         if (fused) HIP_TRY(launch_range_prep(sm, all, window));
@@ -584,8 +612,29 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     }
     HIP_TRY(hipMemcpyAsync(h_out, all.work, hs_work, hipMemcpyDeviceToHost, sm));
     if (hs_feat) HIP_TRY(hipMemcpyAsync(h_feat, pool + o_feat, hs_feat, hipMemcpyDeviceToHost, sm));
+    std::vector<uint64_t> h_dh(hist_words);
+    if (hist) HIP_TRY(hipMemcpyAsync(h_dh.data(), pool + o_dh, sizeof(uint64_t) * hist_words, hipMemcpyDeviceToHost, sm));
     HIP_TRY(hipStreamSynchronize(sm));
     tm.collect();
+    if (hist) {
+        // P_j(l) = prefix over thresholds of the difference counts; rows in caller order
+        const uint32_t kc = job.hist_kp + 1, L = job.hist_len;
+        job.hist.assign((size_t)S * K * L, 0);
+        std::vector<int64_t> run(kc);
+        for (uint32_t i = 0; i < S; ++i) {
+            const uint32_t s = order[i];
+            const SeriesWork& w = h_out[i];
+            for (uint32_t l = 0; l < L; ++l) {
+                const uint64_t* d = &h_dh[((size_t)i * L + l) * kc];
+                int64_t acc = 0;
+                for (uint32_t j = 0; j < kc; ++j) {
+                    acc += (int64_t)d[j];
+                    run[j] = acc;
+                }
+                for (uint32_t r = 0; r < K; ++r) job.hist[((size_t)s * K + r) * L + l] = (uint64_t)run[w.dmap[r]];
+            }
+        }
+    }
 
     // results, back in caller order
     job.eps.assign((size_t)S * K, 0.f);
@@ -664,7 +713,7 @@ rqa_status check_flags_select(uint32_t flags, int* sel)
 {
     const uint32_t known = RQA_SEL_LEARNED | RQA_FULL_HIST | RQA_SEL_SAMPLE | RQA_SEL_WINDOW;
     if (flags & ~known) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
-    if (flags & RQA_FULL_HIST) return fail(RQA_ERR_UNSUPPORTED, "RQA_FULL_HIST is not implemented");
+    if (flags & RQA_FULL_HIST) return fail(RQA_ERR_UNSUPPORTED, "RQA_FULL_HIST is a flag of rqa_det_curve only");
     const uint32_t m = flags & (RQA_SEL_LEARNED | RQA_SEL_SAMPLE | RQA_SEL_WINDOW);
     if (m & (m - 1)) return fail(RQA_ERR_INVALID_ARG, "choose one selection method");
     *sel = (m == RQA_SEL_LEARNED) ? 1 : (m == RQA_SEL_SAMPLE) ? 2 : (m == RQA_SEL_WINDOW) ? 3 : 0;
@@ -1088,13 +1137,41 @@ rqa_status rqa_det_curve(rqa_ctx* c, const float* series, uint64_t n, const rqa_
                          double* det_mean_out, uint64_t* hist_out, uint64_t hist_len)
 {
     if (c) reset_phases(c);
-    if (flags & RQA_FULL_HIST || hist_out || hist_len)
-        return fail(RQA_ERR_UNSUPPORTED, "the full line-length histogram is not implemented");
-    if (flags) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(uint32_t)RQA_FULL_HIST) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const bool full = (flags & RQA_FULL_HIST) != 0;
+    if (!full && (hist_out || hist_len)) return fail(RQA_ERR_INVALID_ARG, "hist_out/hist_len need RQA_FULL_HIST");
+    if (full && !hist_out) return fail(RQA_ERR_INVALID_ARG, "RQA_FULL_HIST with hist_out NULL");
+    if (full && (hist_len < 1 || hist_len > RQA_MAX_HIST_LEN))
+        return fail(RQA_ERR_INVALID_ARG, "hist_len=%llu outside 1..%u", (unsigned long long)hist_len,
+                    (unsigned)RQA_MAX_HIST_LEN);
     if (!count_out || !rr_out || !det_out || !det_mean_out) return fail(RQA_ERR_INVALID_ARG, "an output is NULL");
     Job job;
     rqa_status st = single_job(c, job, series, n, p, nullptr, eps, K, MODE_SWEEP);
     if (st) return st;
+    if (full) {
+        // distinct thresholds (the kernel packs ranks into 8 bits and keeps one
+        // stack entry per rank) and positions below 2^24 - 1
+        std::vector<uint32_t> d(job.eps_bits);
+        std::sort(d.begin(), d.end());
+        const uint32_t kp = (uint32_t)(std::unique(d.begin(), d.end()) - d.begin());
+        if (kp > HIST_MAX_K_HOST)
+            return fail(RQA_ERR_UNSUPPORTED, "%u distinct thresholds; the full histogram takes at most %u", kp,
+                        (unsigned)HIST_MAX_K_HOST);
+        const uint64_t nv = n - (uint64_t)(p->m - 1) * p->tau;
+        if (nv >= (1ull << 24) - 1)
+            return fail(RQA_ERR_UNSUPPORTED, "%llu embedded vectors; the full histogram takes fewer than 2^24 - 1",
+                        (unsigned long long)nv);
+        Job hj;
+        hj.series = job.series;
+        hj.base = job.base;
+        hj.K = K;
+        hj.mode = MODE_HIST;
+        hj.eps_bits = job.eps_bits;
+        hj.hist_len = (uint32_t)hist_len;
+        hj.hist_kp = kp;
+        if ((st = run_job(c, hj))) return st;
+        std::memcpy(hist_out, hj.hist.data(), sizeof(uint64_t) * (size_t)K * hist_len);
+    }
     for (uint32_t r = 0; r < K; ++r) {
         count_out[r] = job.count[r];
         rr_out[r] = job.rr[r];

@@ -1445,6 +1445,212 @@ hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ full line-length histogram
+
+// Full line-length histogram P_j(l) at given thresholds (the histogram behind
+// Eq. 4; L and L_max follow from it).  A tile is one band of whole diagonals
+// (one segment per diagonal), so no line crosses a tile.  Each lane keeps, in
+// its own LDS column, a stack of the cells that were larger in rank than every
+// later cell so far ("previous greater" chain): ranks strictly decrease from
+// the bottom (a sentinel above every rank) to the top.  A new cell of rank r at
+// position t pops every entry of rank <= r; popping entry (r_i, p_i) with
+// (r_n, p_n) below it ends, for every threshold j in [r_i, min(r_n, r)), the
+// line of cells p_n + 1 .. t - 1 (length t - 1 - p_n): at threshold j the last
+// cell not recurrent before t is p_n.  That is one +1 / -1 pair in a
+// difference histogram over j for that length, so the work per cell is
+// amortised O(1) whatever the number of thresholds; P_j(l) is the prefix sum
+// over j.  The end of a diagonal is a cell of rank Kp (recurrent at none).
+// Entries pack (rank << 24) | (position + 1).
+constexpr uint32_t HIST_SHORT = 64;     // lengths below this count in LDS
+constexpr uint32_t HIST_MAX_K = RQA_MAX_HIST_K;  // distinct thresholds
+constexpr uint32_t HIST_BLOCK = 256;
+static_assert(HIST_BLOCK == HIST_BLOCK_HOST && HIST_MAX_K == HIST_MAX_K_HOST, "histogram launch constants");
+static_assert(HIST_MAX_K + 1 < 256, "ranks are packed into 8 bits");
+
+__host__ __device__ __forceinline__ size_t hist_lds_bytes_dev(uint32_t Kp)
+{
+    return RHO_TABLE * sizeof(uint2) + RANK_MAX * 4 + (size_t)(Kp + 2) * HIST_BLOCK * 4 +
+           (size_t)HIST_SHORT * (Kp + 1) * 4;
+}
+
+template <int NORM, int MC, int TC>
+struct HistBody {
+    uint2* stab;          // LDS [RHO_TABLE]
+    uint32_t* ses;        // LDS [RANK_MAX]
+    uint32_t* stk;        // LDS [Kp + 2][blockDim] stacks (column = thread)
+    uint32_t* dsh;        // LDS [HIST_SHORT][Kp + 1] difference counts of short lines
+    const uint2* rtab;
+    SeriesWork* works;
+    uint64_t* dglob;      // global [S][hist_len][Kp + 1] difference counts (signed, two's complement)
+    uint32_t hist_len;
+    uint32_t kcap;        // Kp + 1 of the launch (row stride)
+    RhoCtx rc;
+    uint64_t* dser;       // this series' rows
+    bool multi;
+    bool active = true;
+    // lane state
+    uint32_t top_r = 0, top_p = 0, sp = 0;
+
+    __device__ void begin(uint32_t s)
+    {
+        const SeriesWork& w = works[s];
+        for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RHO_TABLE + i];
+        for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) ses[i] = w.esorted[i];
+        for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) dsh[i] = 0u;
+        rc.table = stab;
+        rc.es = ses;
+        rc.emin = __uint_as_float(uniform(w.emin));
+        rc.emax = __uint_as_float(uniform(w.emax));
+        rc.shift = uniform(w.shift);
+        rc.Kp = uniform(w.Kp);
+        rc.z = 0;
+        multi = uniform(w.multi) != 0;
+        active = uniform(w.nonfinite) == 0u;  // no ranks for a series with NaN or infinite samples
+        dser = dglob + (size_t)s * hist_len * kcap;
+    }
+    __device__ void flush(uint32_t)
+    {
+        for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) {
+            const uint32_t l = i / kcap, j = i % kcap;
+            const int32_t v = (int32_t)dsh[i];
+            if (v && l < hist_len)
+                atomicAdd((unsigned long long*)&dser[(size_t)l * kcap + j], (unsigned long long)(int64_t)v);
+        }
+    }
+    // one line of length l at thresholds [a, b)
+    __device__ __forceinline__ void line(uint32_t l, uint32_t a, uint32_t b)
+    {
+        const uint32_t lb = min(l, hist_len - 1);
+        if (lb < HIST_SHORT) {
+            atomicAdd(&dsh[lb * kcap + a], 1u);
+            atomicAdd(&dsh[lb * kcap + b], 0xFFFFFFFFu);
+        } else {
+            atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + a], 1ull);
+            atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + b], ~0ull);
+        }
+    }
+    // cell of rank r at position t (t < 2^24 - 1)
+    __device__ __forceinline__ void cell(uint32_t r, uint32_t t)
+    {
+        uint32_t* col = stk + threadIdx.x;
+        while (top_r <= r) {
+            const uint32_t nx = col[(size_t)(sp - 1) * blockDim.x];
+            const uint32_t nr = nx >> 24, np1 = nx & 0xFFFFFFu;   // np1 = position + 1
+            const uint32_t b = min(nr, r);
+            if (top_r < b) line(t - np1, top_r, b);
+            top_r = nr;
+            top_p = np1;
+            --sp;
+        }
+        col[(size_t)sp * blockDim.x] = (top_r << 24) | top_p;
+        ++sp;
+        top_r = r;
+        top_p = t + 1;
+    }
+    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        if (multi) tile_impl<true>(sd, tile_id, lane);
+        else tile_impl<false>(sd, tile_id, lane);
+    }
+    template <bool MULTI>
+    __device__ __forceinline__ void tile_impl(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    {
+        const TileGeo g = tile_geo(sd, tile_id, lane);
+        const uint32_t Kp = rc.Kp;
+        // sentinel: rank above every cell, position -1
+        top_r = Kp + 1;
+        top_p = 0;
+        sp = 0;
+        int x = 0;
+        constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
+        if constexpr (kFast) {
+            constexpr int TW = MC == 1 ? 1 : TC;
+            constexpr int HU = walk_block<NORM, MC, TW>();
+            // every lane's diagonal covers [0, L + WALK_SLACK)
+            const int L = g.len0 - TILE_W - WALK_SLACK;
+            if (L > 0) {
+                const RhoCtx c = rc;
+                int t = 0;
+                walk<NORM, MC, TW>(sd.y, g.d, 0, L, [&](const uint32_t(&k)[HU], int valid) {
+#pragma unroll
+                    for (int u = 0; u < HU; ++u)
+                        if (u < valid) cell(min(rho_of<MULTI>(k[u], c), Kp), (uint32_t)(t + u));
+                    t += HU;
+                });
+                x = L;
+            }
+        }
+        // the rest of the band, then the end of every diagonal (rank Kp)
+        for (; x <= g.len0; ++x) {
+            uint32_t r = Kp;
+            if (x < g.len)
+                r = min(rho_of<MULTI>(__float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau)), rc), Kp);
+            cell(r, (uint32_t)x);
+        }
+    }
+};
+
+template <int NORM, int MC, int TC>
+__global__ void __launch_bounds__(HIST_BLOCK)
+k_hist(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
+       uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
+       uint64_t* __restrict__ dglob, uint32_t hist_len, uint32_t Kp)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    HistBody<NORM, MC, TC> body;
+    body.stab = (uint2*)smem;
+    body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
+    body.stk = body.ses + RANK_MAX;
+    body.dsh = body.stk + (size_t)(Kp + 2) * HIST_BLOCK;
+    body.rtab = rtab;
+    body.works = works;
+    body.dglob = dglob;
+    body.hist_len = hist_len;
+    body.kcap = Kp + 1;
+    body.multi = false;
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + hist_lds_bytes_dev(Kp)));
+}
+
+size_t hist_lds_bytes(uint32_t Kp) { return hist_lds_bytes_dev(Kp) + 16; }
+
+using HistFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint2*,
+                        uint64_t*, uint32_t, uint32_t);
+
+template <int NORM>
+static HistFn hist_fn_n(int mclass)
+{
+    switch (mclass) {
+    case 1: return k_hist<NORM, 1, 0>;
+    case 2: return k_hist<NORM, 3, 3>;
+    case 3: return k_hist<NORM, 3, 5>;
+    default: return k_hist<NORM, 0, 0>;
+    }
+}
+
+static HistFn hist_fn(int select_variant)
+{
+    const int norm = select_variant / NUM_MCLASS, mc = select_variant % NUM_MCLASS;
+    return norm == RQA_NORM_MAX ? hist_fn_n<RQA_NORM_MAX>(mc) : hist_fn_n<RQA_NORM_EUCLIDEAN>(mc);
+}
+
+hipError_t launch_hist(hipStream_t st, const DevBufs& b, int select_variant, uint32_t grid, uint64_t* dglob,
+                       uint32_t hist_len, uint32_t Kp, uint32_t ticket)
+{
+    hipLaunchKernelGGL(hist_fn(select_variant), dim3(grid), dim3(HIST_BLOCK), hist_lds_bytes(Kp), st, b.sd, b.S,
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, dglob, hist_len, Kp);
+    return hipGetLastError();
+}
+
+int hist_blocks_per_cu(int select_variant, uint32_t Kp)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hist_fn(select_variant), (int)HIST_BLOCK,
+                                                     hist_lds_bytes(Kp)) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+
 // Range table of one series over the ascending boundaries es[0..kp) with rank
 // base z: RANGE_TABLE buckets of 2^shift bit patterns from es[0] to
 // es[kp-1]; each holds the first two boundaries inside it (x, y; ~0 when
@@ -2110,6 +2316,7 @@ hipError_t set_kernel_lds_limits(size_t max_dyn_lds)
             set((const void*)sweep_fn(v * 3 + l));
             set((const void*)range_fn(v * 3 + l));
         }
+        set((const void*)hist_fn(v));
     }
     return err;
 }

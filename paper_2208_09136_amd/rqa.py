@@ -26,7 +26,7 @@ STATUS = {0: "RQA_OK", -1: "RQA_ERR_INVALID_ARG", -2: "RQA_ERR_TOO_SHORT",
           -3: "RQA_ERR_NONFINITE", -4: "RQA_ERR_DEVICE", -5: "RQA_ERR_NOMEM",
           -6: "RQA_ERR_UNSUPPORTED"}
 
-PHASES = ("select_pass1", "select_pass2", "select_pass3", "sweep", "other")
+PHASES = ("select_pass1", "select_pass2", "select_pass3", "sweep", "other", "histogram")
 
 
 class RqaError(RuntimeError):
@@ -318,8 +318,11 @@ def rqa_select_thresholds(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
     return eps, k, cnt
 
 
-def rqa_det_curve(ctx, series, params, eps, flags=0):
-    """RR and DET at the given thresholds: dict(count, rr, det, det_mean)."""
+def rqa_det_curve(ctx, series, params, eps, flags=0, hist_len=0):
+    """RR and DET at the given thresholds: dict(count, rr, det, det_mean,
+    hist).  hist_len > 0 sets RQA_FULL_HIST and returns hist, a (K, hist_len)
+    uint64 array of P_r(l) (the last entry collects longer lines); else hist
+    is None."""
     ptr, n = _series_ptr(series)
     eps = _a(eps, np.float32)
     K = len(eps)
@@ -327,11 +330,15 @@ def rqa_det_curve(ctx, series, params, eps, flags=0):
     rr = np.zeros(K, np.float64)
     det = np.zeros(K, np.float64)
     dm = np.zeros(1, np.float64)
+    hist = np.zeros((K, hist_len), np.uint64) if hist_len else None
+    if hist_len:
+        flags |= RQA_FULL_HIST
     prm = _params(params)
     _check(load().rqa_det_curve(ctx, ptr, n, ctypes.byref(prm), _p(eps, ctypes.c_float), K, flags,
                                 _p(cnt, ctypes.c_uint64), _p(rr, ctypes.c_double), _p(det, ctypes.c_double),
-                                _p(dm, ctypes.c_double), None, 0))
-    return {"count": cnt, "rr": rr, "det": det, "det_mean": float(dm[0])}
+                                _p(dm, ctypes.c_double), _p(hist, ctypes.c_uint64) if hist_len else None,
+                                hist_len))
+    return {"count": cnt, "rr": rr, "det": det, "det_mean": float(dm[0]), "hist": hist}
 
 
 def rqa_run(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
@@ -402,8 +409,8 @@ class Context:
     def select_thresholds(self, series, params, rr, flags=RQA_SEL_PLAIN):
         return rqa_select_thresholds(self.ctx, series, params, rr, flags)
 
-    def det_curve(self, series, params, eps, flags=0):
-        return rqa_det_curve(self.ctx, series, params, eps, flags)
+    def det_curve(self, series, params, eps, flags=0, hist_len=0):
+        return rqa_det_curve(self.ctx, series, params, eps, flags, hist_len)
 
     def run(self, series, params, rr, flags=RQA_SEL_PLAIN):
         return rqa_run(self.ctx, series, params, rr, flags)

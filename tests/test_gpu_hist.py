@@ -1,0 +1,177 @@
+"""Full diagonal line-length histogram P_r(l) (the histogram behind Eq. 4):
+element-by-element equal to the oracle's at every threshold, for every kernel
+variant, with ties, repeated, zero and infinite thresholds, lumped and
+unlumped tails, and at the full N = 10^5 size through the identities
+sum_l l P(l) = C and sum_{l >= lmin} l P(l) = D of the sweep."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FULL_HIST = 2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2208_09136_amd import rqa
+    c = rqa.Context(0, torch.cuda.current_stream())
+    yield c
+    c.close()
+
+
+def dev(y):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to("cuda:0")
+
+
+def nv_of(n, m, tau):
+    return n - (m - 1) * tau
+
+
+def eps_set(y, m, tau, norm, w, rr):
+    return oracle.select(y, m, tau, norm, w, rr)[0]
+
+
+def case(name, y, m, tau, norm, w, lmin, eps):
+    return dict(name=name, y=np.asarray(y, np.float32), m=m, tau=tau, norm=norm, w=w, lmin=lmin,
+                eps=np.asarray(eps, np.float32))
+
+
+def cases():
+    out = []
+    rr = np.linspace(0.01, 0.2, 20)
+    # m = 1 (logistic, max norm)
+    c = synth.config_small(5)
+    out.append(case("logistic_m1_max", c["y"], 1, 1, 0, 1, 2, eps_set(c["y"], 1, 1, 0, 1, rr)))
+    # long lines: lightly noisy sine, Euclidean, m = 1
+    y = synth.series("sine", 3000, 20.0, (7, 0, 0, 1))
+    out.append(case("sine_m1_euclid", y, 1, 1, 1, 1, 2, eps_set(y, 1, 1, 1, 1, rr)))
+    # m = 3, tau = 5, Theiler window 5, lmin 3, repeated / zero / infinite thresholds
+    y = synth.series("lorenz", 2500, 10.0, (7, 1, 0, 2))
+    e = eps_set(y, 3, 5, 1, 5, rr[::2])
+    e = np.concatenate([e, e[:3], [0.0, np.inf]]).astype(np.float32)
+    out.append(case("lorenz_m3t5_w5_dups", y, 3, 5, 1, 5, 3, e))
+    # m = 3, tau = 3 and the generic walker (m = 2, tau = 7), ragged lengths
+    y = synth.series("logistic", 1733, 0.0, (7, 2, 0, 3))
+    out.append(case("logistic_m3t3_max", y, 3, 3, 0, 1, 2, eps_set(y, 3, 3, 0, 1, rr)))
+    y = synth.series("lorenz", 1701, -10.0, (7, 3, 0, 4))
+    out.append(case("lorenz_m2t7_w3", y, 2, 7, 1, 3, 4, eps_set(y, 2, 7, 1, 3, rr[::3])))
+    # integer series: many keys equal to the thresholds
+    y = synth.periodic_integer(1200, 17, seed=3)
+    out.append(case("periodic_ties", y, 2, 1, 0, 1, 2, np.array([0, 1, 2, 3, 5, 8], np.float32)))
+    # 32 distinct thresholds, the most one call takes
+    c = synth.config_small(6)
+    out.append(case("logistic_k32", c["y"], 1, 1, 1, 2, 2,
+                    eps_set(c["y"], 1, 1, 1, 2, np.linspace(0.005, 0.6, 32))))
+    return out
+
+
+CASES = cases()
+
+
+@pytest.mark.parametrize("idx", range(len(CASES)))
+def test_histogram_equals_oracle(ctx, idx):
+    c = CASES[idx]
+    p = (c["m"], c["tau"], c["norm"], c["w"], c["lmin"])
+    nv = nv_of(len(c["y"]), c["m"], c["tau"])
+    y = dev(c["y"])
+    plain = ctx.det_curve(y, p, c["eps"])
+    for hl in (nv + 1, 16, 2, 1):
+        print(f"[hist] {c['name']} hist_len={hl}", flush=True)
+        got = ctx.det_curve(y, p, c["eps"], hist_len=hl)
+        want = oracle.lines(c["y"], c["m"], c["tau"], c["norm"], c["w"], c["lmin"], c["eps"], hist_len=hl)
+        assert got["hist"].shape == (len(c["eps"]), hl)
+        assert np.array_equal(got["hist"], want["hist"]), hl
+        # the other outputs do not change with the histogram
+        for key in ("count", "rr"):
+            assert np.array_equal(got[key], plain[key]), key
+        assert np.array_equal(got["det"], plain["det"], equal_nan=True)
+    # identities of the unlumped histogram
+    h = ctx.det_curve(y, p, c["eps"], hist_len=nv + 1)["hist"].astype(np.int64)
+    l = np.arange(nv + 1, dtype=np.int64)
+    assert np.array_equal((h * l).sum(axis=1).astype(np.uint64), plain["count"])
+    D = (h[:, c["lmin"]:] * l[c["lmin"]:]).sum(axis=1)
+    for r in range(len(c["eps"])):
+        if plain["count"][r]:
+            assert D[r] == round(plain["det"][r] * float(plain["count"][r]))
+        else:
+            assert D[r] == 0
+
+
+def test_infinite_threshold_closed_form(ctx):
+    # at eps = +inf every diagonal j - i = d (theiler <= d < nv) is one line of nv - d pairs
+    y = synth.series("logistic", 900, 10.0, (7, 4, 0, 5))
+    m, tau, w = 2, 3, 4
+    nv = nv_of(len(y), m, tau)
+    got = ctx.det_curve(dev(y), (m, tau, 1, w, 2), [np.inf], hist_len=nv + 2)["hist"][0]
+    want = np.zeros(nv + 2, np.uint64)
+    want[1:nv - w + 1] = 1
+    assert np.array_equal(got, want)
+    # at eps below every key there is no line
+    got = ctx.det_curve(dev(y + np.arange(len(y), dtype=np.float32) * 10), (m, tau, 1, w, 2), [0.0],
+                        hist_len=50)["hist"][0]
+    assert not got.any()
+
+
+def test_launch_shape_does_not_change_histogram(ctx):
+    c = CASES[2]
+    p = (c["m"], c["tau"], c["norm"], c["w"], c["lmin"])
+    y = dev(c["y"])
+    ref = ctx.det_curve(y, p, c["eps"], hist_len=300)["hist"]
+    try:
+        for g in (1, 3, 17):
+            ctx.set_grid(g)
+            assert np.array_equal(ctx.det_curve(y, p, c["eps"], hist_len=300)["hist"], ref), g
+    finally:
+        ctx.set_grid(0)
+
+
+def test_histogram_limits(ctx):
+    from paper_2208_09136_amd.rqa import RqaError
+    c = synth.config_small(1)
+    y = dev(c["y"])
+    p = (1, 1, 0, 1, 2)
+    e33 = eps_set(c["y"], 1, 1, 0, 1, np.linspace(0.01, 0.5, 33))
+    assert len(np.unique(e33)) == 33
+    with pytest.raises(RqaError) as e:
+        ctx.det_curve(y, p, e33, hist_len=10)
+    assert e.value.name == "RQA_ERR_UNSUPPORTED"
+    # 33 thresholds with 32 distinct values are accepted
+    e = np.concatenate([e33[:32], e33[:1]])
+    got = ctx.det_curve(y, p, e, hist_len=10)
+    want = oracle.lines(c["y"], 1, 1, 0, 1, 2, e, hist_len=10)
+    assert np.array_equal(got["hist"], want["hist"])
+    # flag without an output buffer
+    with pytest.raises(RqaError) as e:
+        ctx.det_curve(y, p, e33[:3], flags=FULL_HIST)
+    assert e.value.name == "RQA_ERR_INVALID_ARG"
+    bad = c["y"].copy()
+    bad[10] = np.nan
+    with pytest.raises(RqaError) as e:
+        ctx.det_curve(dev(bad), p, e33[:3], hist_len=10)
+    assert e.value.name == "RQA_ERR_NONFINITE"
+    # the context still works afterwards
+    got = ctx.det_curve(y, p, e33[:3], hist_len=10)
+    assert np.array_equal(got["hist"], oracle.lines(c["y"], 1, 1, 0, 1, 2, e33[:3], hist_len=10)["hist"])
+
+
+def test_full_size_identities(ctx):
+    # N = 10^5, m = 3, tau = 5, Euclidean: the workload's size, checked through
+    # sum_l l P(l) = C and sum_{l >= lmin} l P(l) = D from the sweep
+    c = synth.config_large(which="lorenz")[0]
+    p = (c["m"], c["tau"], c["norm"], c["theiler"], c["lmin"])
+    y = dev(c["y"])
+    eps = ctx.select_thresholds(y, p, c["rr"])[0]
+    nv = nv_of(len(c["y"]), c["m"], c["tau"])
+    print(f"[hist] {c['name']} full size", flush=True)
+    got = ctx.det_curve(y, p, eps, hist_len=nv + 1)
+    h = got["hist"].astype(np.int64)
+    l = np.arange(nv + 1, dtype=np.int64)
+    assert np.array_equal((h * l).sum(axis=1).astype(np.uint64), got["count"])
+    D = (h[:, c["lmin"]:] * l[c["lmin"]:]).sum(axis=1)
+    assert np.array_equal(D, np.round(got["det"] * got["count"].astype(np.float64)).astype(np.int64))
+    assert (h[:, 0] == 0).all() and (h >= 0).all()
