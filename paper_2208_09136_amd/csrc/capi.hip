@@ -181,6 +181,16 @@ uint32_t segment_for(const rqa_ctx* c, uint64_t nv, const rqa_params& p, uint32_
     return default_segment(nv - p.theiler);
 }
 
+// Segment of the histogram pass: the caller's override (at most
+// HIST_MAX_SEG_HOST), else about 48 segments on the longest diagonal
+// (256 .. 4096).
+uint32_t hist_segment_for(const rqa_ctx* c, uint64_t L0)
+{
+    if (c->seg) return std::min<uint32_t>(c->seg, HIST_MAX_SEG_HOST);
+    const uint64_t t = (L0 + 47) / 48;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>((t + TILE_W - 1) / TILE_W * TILE_W, 256), 4096);
+}
+
 uint32_t chunk_for(const rqa_ctx* c, uint32_t S, uint64_t nv0, const rqa_params& p0, uint32_t K)
 {
     if (c->chunk_tiles) return c->chunk_tiles;
@@ -294,10 +304,21 @@ rqa_status run_job(rqa_ctx* c, Job& job)
 {
     const uint32_t S = (uint32_t)job.series.size();
     const uint32_t K = job.K;
+    const bool hist = (job.mode & MODE_HIST) != 0;
+    // histogram pass: the largest workgroup whose stacks fit in LDS, one tile per wave and chunk
+    uint32_t hist_block = 0;
+    if (hist) {
+        for (uint32_t b : {1024u, 512u, 256u, 128u, 64u})
+            if (hist_lds_bytes(job.hist_kp, b) <= c->max_lds) {
+                hist_block = b;
+                break;
+            }
+        if (!hist_block) return fail(RQA_ERR_UNSUPPORTED, "the histogram pass does not fit in LDS");
+    }
     uint32_t CT;
     {
         const Series& z0 = job.series[0];
-        CT = (job.mode & MODE_HIST) ? (uint32_t)(HIST_BLOCK_HOST / TILE_W) : chunk_for(c, S, z0.n - (uint64_t)(z0.p.m - 1) * z0.p.tau, z0.p, K);
+        CT = hist ? hist_block / TILE_W : chunk_for(c, S, z0.n - (uint64_t)(z0.p.m - 1) * z0.p.tau, z0.p, K);
     }
 
     // descriptors, ordered by kernel variant so each launch sees a contiguous range
@@ -337,9 +358,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
         const uint64_t L0 = nv - z.p.theiler;
         SeriesDesc& d = sd[i];
-        // histogram mode: one segment per diagonal, so no line crosses a tile
-        const uint32_t T = (job.mode & MODE_HIST) ? (uint32_t)((L0 + TILE_W - 1) / TILE_W * TILE_W)
-                                                  : segment_for(c, nv, z.p, K);
+        const uint32_t T = hist ? hist_segment_for(c, L0) : segment_for(c, nv, z.p, K);
         d.y = job.base + z.offset;
         d.n = (uint32_t)z.n;
         d.nv = (uint32_t)nv;
@@ -393,9 +412,18 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
     const bool window = (job.mode & MODE_SELECT) && job.sel != 0;
     const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
-    const bool hist = (job.mode & MODE_HIST) != 0;
     const size_t hist_words = hist ? (size_t)S * job.hist_len * (job.hist_kp + 1) : 0;
     const size_t o_dh = hist ? carve(sizeof(uint64_t) * hist_words) : 0;
+    // histogram: leading / trailing runs per tile, threshold and lane (written before read)
+    std::vector<size_t> g_tile(groups.size(), 0);
+    size_t hist_tiles = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        g_tile[gi] = hist_tiles;
+        hist_tiles += (size_t)groups[gi].nchunks * CT;
+    }
+    const size_t run_words = hist ? hist_tiles * (job.hist_kp + 1) * TILE_W : 0;
+    const size_t o_pre = hist ? carve(sizeof(uint16_t) * run_words) : 0;
+    const size_t o_suf = hist ? carve(sizeof(uint16_t) * run_words) : 0;
     const size_t zero_end = off;  // tickets and histograms are cleared every call
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
@@ -574,15 +602,23 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         HIP_TRY(launch_sweep_prep(sm, all));
         HIP_TRY(tm.end());
         HIP_TRY(tm.begin(PH_HIST));
-        for (const Group& g : groups) {
+        const uint32_t kc = job.hist_kp + 1;
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group& g = groups[gi];
             DevBufs v = view(g);
-            const int per_cu = hist_blocks_per_cu(g.sel, job.hist_kp);
+            const int per_cu = hist_blocks_per_cu(g.sel, job.hist_kp, hist_block);
             const uint32_t grid = c->grid ? c->grid
                                           : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
             const int t = take(1);
             if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-            HIP_TRY(launch_hist(sm, v, g.sel, grid, (uint64_t*)(pool + o_dh) + (size_t)g.begin * job.hist_len * (job.hist_kp + 1),
-                                job.hist_len, job.hist_kp, (uint32_t)t));
+            uint64_t* dg = (uint64_t*)(pool + o_dh) + (size_t)g.begin * job.hist_len * kc;
+            uint16_t* pre = (uint16_t*)(pool + o_pre) + g_tile[gi] * kc * TILE_W;
+            uint16_t* suf = (uint16_t*)(pool + o_suf) + g_tile[gi] * kc * TILE_W;
+            HIP_TRY(launch_hist(sm, v, g.sel, grid, hist_block, dg, pre, suf, job.hist_len, job.hist_kp, (uint32_t)t));
+            uint32_t items = 1;
+            for (uint32_t i = g.begin; i < g.end; ++i) items = std::max(items, sd[i].B * ((job.hist_kp + 3) / 4));
+            const uint32_t jgrid = std::min<uint32_t>(items, (uint32_t)c->num_cu * 4);
+            HIP_TRY(launch_hist_join(sm, v, jgrid, pre, suf, dg, job.hist_len, job.hist_kp));
         }
         HIP_TRY(tm.end());
     }

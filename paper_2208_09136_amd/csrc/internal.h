@@ -166,16 +166,22 @@ hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, bool rang
 // scan 1 (window = true); and the final scan giving eps, C and D.
 hipError_t launch_range_prep(hipStream_t st, const DevBufs& b, bool window);
 hipError_t launch_range_scan(hipStream_t st, const DevBufs& b);
-// Full line-length histogram at given thresholds (after k_sweep_prep): bands
-// of whole diagonals (one segment per diagonal), difference counts
-// dglob[S][hist_len][Kp + 1] (two's complement in uint64; cleared by the
-// caller).  Kp <= HIST_MAX_K distinct thresholds.
-hipError_t launch_hist(hipStream_t st, const DevBufs& b, int select_variant, uint32_t grid, uint64_t* dglob,
-                       uint32_t hist_len, uint32_t Kp, uint32_t ticket);
-size_t hist_lds_bytes(uint32_t Kp);
-int hist_blocks_per_cu(int select_variant, uint32_t Kp);
+// Full line-length histogram at given thresholds (after k_sweep_prep) over
+// the (band, segment) tiles: difference counts dglob[S][hist_len][Kp + 1]
+// (two's complement in uint64; cleared by the caller) of the lines inside a
+// segment, and per tile, threshold and lane the leading and trailing run
+// lengths pre / suf [tiles][Kp + 1][64] (tile index = chunk_begin *
+// chunk_tiles + tile, per group); the join adds the lines across segment
+// borders.  Kp <= HIST_MAX_K_HOST distinct thresholds, segments at most
+// HIST_MAX_SEG_HOST long, block a multiple of 64 up to 1024.
+hipError_t launch_hist(hipStream_t st, const DevBufs& b, int select_variant, uint32_t grid, uint32_t block,
+                       uint64_t* dglob, uint16_t* pre, uint16_t* suf, uint32_t hist_len, uint32_t Kp, uint32_t ticket);
+hipError_t launch_hist_join(hipStream_t st, const DevBufs& b, uint32_t grid, const uint16_t* pre,
+                            const uint16_t* suf, uint64_t* dglob, uint32_t hist_len, uint32_t Kp);
+size_t hist_lds_bytes(uint32_t Kp, uint32_t block);
+int hist_blocks_per_cu(int select_variant, uint32_t Kp, uint32_t block);
 constexpr uint32_t HIST_MAX_K_HOST = RQA_MAX_HIST_K;
-constexpr uint32_t HIST_BLOCK_HOST = 256;
+constexpr uint32_t HIST_MAX_SEG_HOST = 32768;
 // Window selection.  Sources of the window: predicted offsets [S][20] with
 // half-widths (network), or the sorted sketch sample (sample quantiles).
 struct WinBufs {

@@ -1448,28 +1448,33 @@ hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
 // ------------------------------------------------------------------ full line-length histogram
 
 // Full line-length histogram P_j(l) at given thresholds (the histogram behind
-// Eq. 4; L and L_max follow from it).  A tile is one band of whole diagonals
-// (one segment per diagonal), so no line crosses a tile.  Each lane keeps, in
-// its own LDS column, a stack of the cells that were larger in rank than every
+// Eq. 4).  Tiles are the (band, segment) tiles of the sweep.  Each lane keeps
+// a stack of the cells of its segment that were larger in rank than every
 // later cell so far ("previous greater" chain): ranks strictly decrease from
-// the bottom (a sentinel above every rank) to the top.  A new cell of rank r at
-// position t pops every entry of rank <= r; popping entry (r_i, p_i) with
-// (r_n, p_n) below it ends, for every threshold j in [r_i, min(r_n, r)), the
-// line of cells p_n + 1 .. t - 1 (length t - 1 - p_n): at threshold j the last
-// cell not recurrent before t is p_n.  That is one +1 / -1 pair in a
-// difference histogram over j for that length, so the work per cell is
-// amortised O(1) whatever the number of thresholds; P_j(l) is the prefix sum
-// over j.  The end of a diagonal is a cell of rank Kp (recurrent at none).
-// Entries pack (rank << 24) | (position + 1).
+// the bottom (a sentinel at position t0 - 1, above every rank) to the top.
+// A new cell of rank r at position t pops every entry of rank <= r; popping
+// entry (r_i, p_i) with (r_n, p_n) below it ends, for every threshold j in
+// [r_i, min(r_n, r)), the run of cells p_n + 1 .. t - 1 (at threshold j the
+// last cell before t that is not recurrent is p_n).  A run inside the
+// segment is a line: one +1 / -1 pair in a difference histogram over j for
+// its length, so the work per cell is amortised O(1) whatever the number of
+// thresholds, and P_j(l) is the prefix sum over j.  A run that starts at the
+// segment's first cell (p_n is the sentinel) or ends at its last may continue
+// in the neighbouring segment: per lane and threshold the segment records
+// the length of its leading run (pre_j) and trailing run (suf_j), and a join
+// pass walks each diagonal's segments in order and counts the lines that
+// cross segment borders.  Cells past the end of a diagonal have rank Kp
+// (recurrent at no threshold).  The top two stack entries live in registers;
+// entries pack (rank << 24) | (position + 1).
 constexpr uint32_t HIST_SHORT = 64;     // lengths below this count in LDS
 constexpr uint32_t HIST_MAX_K = RQA_MAX_HIST_K;  // distinct thresholds
-constexpr uint32_t HIST_BLOCK = 256;
-static_assert(HIST_BLOCK == HIST_BLOCK_HOST && HIST_MAX_K == HIST_MAX_K_HOST, "histogram launch constants");
+static_assert(HIST_MAX_K == HIST_MAX_K_HOST, "histogram limits");
 static_assert(HIST_MAX_K + 1 < 256, "ranks are packed into 8 bits");
+static_assert(HIST_MAX_SEG_HOST < 65536, "run lengths are stored in 16 bits");
 
-__host__ __device__ __forceinline__ size_t hist_lds_bytes_dev(uint32_t Kp)
+__host__ __device__ __forceinline__ size_t hist_lds_bytes_dev(uint32_t Kp, uint32_t block)
 {
-    return RHO_TABLE * sizeof(uint2) + RANK_MAX * 4 + (size_t)(Kp + 2) * HIST_BLOCK * 4 +
+    return RHO_TABLE * sizeof(uint2) + RANK_MAX * 4 + (size_t)(Kp + 1) * block * 4 +
            (size_t)HIST_SHORT * (Kp + 1) * 4;
 }
 
@@ -1477,21 +1482,30 @@ template <int NORM, int MC, int TC>
 struct HistBody {
     uint2* stab;          // LDS [RHO_TABLE]
     uint32_t* ses;        // LDS [RANK_MAX]
-    uint32_t* stk;        // LDS [Kp + 2][blockDim] stacks (column = thread)
+    uint32_t* stk;        // LDS [Kp + 1][blockDim] stack entries below the top two (column = thread)
     uint32_t* dsh;        // LDS [HIST_SHORT][Kp + 1] difference counts of short lines
+    const SeriesDesc* sds;
     const uint2* rtab;
     SeriesWork* works;
-    uint64_t* dglob;      // global [S][hist_len][Kp + 1] difference counts (signed, two's complement)
+    uint64_t* dglob;      // global [S][hist_len][kcap] difference counts (signed, two's complement)
+    uint16_t* pre;        // global [tiles][kcap][64] leading run per threshold
+    uint16_t* suf;        // global [tiles][kcap][64] trailing run per threshold
     uint32_t hist_len;
     uint32_t kcap;        // Kp + 1 of the launch (row stride)
+    uint32_t chunk_tiles;
     RhoCtx rc;
     uint64_t* dser;       // this series' rows
+    uint32_t tbase;       // this series' first tile in pre / suf
     bool multi;
     bool active = true;
-    // lane state
-    uint32_t top_r = 0, top_p = 0, sp = 0;
+    // lane state: top (top_r, top_p) and next (nx_r, nx_p) of the stack; LDS rows
+    // [0, sp) hold the sentinel and then the entries below next (sp >= 1); pm is
+    // the largest rank so far in the segment
+    uint32_t top_r, top_p, nx_r, nx_p, sp, pm, t0;
+    uint16_t* lpre;       // this lane's pre / suf column in the current tile
+    uint16_t* lsuf;
 
-    __device__ void begin(uint32_t s)
+    __device__ __forceinline__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
         for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RHO_TABLE + i];
@@ -1507,8 +1521,9 @@ struct HistBody {
         multi = uniform(w.multi) != 0;
         active = uniform(w.nonfinite) == 0u;  // no ranks for a series with NaN or infinite samples
         dser = dglob + (size_t)s * hist_len * kcap;
+        tbase = uniform(sds[s].chunk_begin) * chunk_tiles;
     }
-    __device__ void flush(uint32_t)
+    __device__ __forceinline__ void flush(uint32_t)
     {
         for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) {
             const uint32_t l = i / kcap, j = i % kcap;
@@ -1529,25 +1544,41 @@ struct HistBody {
             atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + b], ~0ull);
         }
     }
-    // cell of rank r at position t (t < 2^24 - 1)
+    __device__ __forceinline__ uint32_t& row(uint32_t i) { return stk[(size_t)i * blockDim.x + threadIdx.x]; }
+    __device__ __forceinline__ void pop()
+    {
+        top_r = nx_r;
+        top_p = nx_p;
+        // row 0 is the sentinel: below the sentinel is the sentinel again
+        const uint32_t e = row(sp - 1);
+        nx_r = e >> 24;
+        nx_p = e & 0xFFFFFFu;
+        sp = max(sp - 1, 1u);
+    }
+    // cell of rank r <= Kp at position t
     __device__ __forceinline__ void cell(uint32_t r, uint32_t t)
     {
-        uint32_t* col = stk + threadIdx.x;
-        while (top_r <= r) {
-            const uint32_t nx = col[(size_t)(sp - 1) * blockDim.x];
-            const uint32_t nr = nx >> 24, np1 = nx & 0xFFFFFFu;   // np1 = position + 1
-            const uint32_t b = min(nr, r);
-            if (top_r < b) line(t - np1, top_r, b);
-            top_r = nr;
-            top_p = np1;
-            --sp;
+        if (r > pm) {
+            // first cell above thresholds [pm, r): the leading runs there end before t
+#pragma unroll 1
+            for (uint32_t j = pm; j < r; ++j) lpre[(size_t)j * TILE_W] = (uint16_t)(t - t0);
+            pm = r;
         }
-        col[(size_t)sp * blockDim.x] = (top_r << 24) | top_p;
-        ++sp;
+        while (top_r <= r) {
+            // next is the sentinel: a leading run, recorded above
+            const uint32_t b = nx_r > rc.Kp ? top_r : min(nx_r, r);
+            if (top_r < b) line(t - nx_p, top_r, b);
+            pop();
+        }
+        // a cell below the top: next goes to LDS (a sentinel next is row 0 already)
+        row(sp) = (nx_r << 24) | nx_p;
+        sp += nx_r <= rc.Kp ? 1u : 0u;
+        nx_r = top_r;
+        nx_p = top_p;
         top_r = r;
         top_p = t + 1;
     }
-    __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
+    __device__ __forceinline__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
         if (multi) tile_impl<true>(sd, tile_id, lane);
         else tile_impl<false>(sd, tile_id, lane);
@@ -1557,64 +1588,167 @@ struct HistBody {
     {
         const TileGeo g = tile_geo(sd, tile_id, lane);
         const uint32_t Kp = rc.Kp;
-        // sentinel: rank above every cell, position -1
-        top_r = Kp + 1;
-        top_p = 0;
-        sp = 0;
-        int x = 0;
+        const size_t col = ((size_t)(tbase + tile_id) * kcap) * TILE_W + lane;
+        lpre = pre + col;
+        lsuf = suf + col;
+        t0 = (uint32_t)g.t0;
+        // sentinel (rank Kp + 1 at position t0 - 1) as top, next and LDS row 0
+        top_r = nx_r = Kp + 1;
+        top_p = nx_p = t0;
+        row(0) = ((Kp + 1) << 24) | t0;
+        sp = 1;
+        pm = 0;
         constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
+        bool done = false;
         if constexpr (kFast) {
             constexpr int TW = MC == 1 ? 1 : TC;
             constexpr int HU = walk_block<NORM, MC, TW>();
-            // every lane's diagonal covers [0, L + WALK_SLACK)
-            const int L = g.len0 - TILE_W - WALK_SLACK;
-            if (L > 0) {
+            if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
+                // interior: every lane's diagonal covers [t0, t1 + WALK_SLACK]
                 const RhoCtx c = rc;
-                int t = 0;
-                walk<NORM, MC, TW>(sd.y, g.d, 0, L, [&](const uint32_t(&k)[HU], int valid) {
+                uint32_t t = t0;
+                walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    uint32_t rk[HU];
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) rk[u] = min(rho_of<MULTI>(k[u], c), Kp);
 #pragma unroll
                     for (int u = 0; u < HU; ++u)
-                        if (u < valid) cell(min(rho_of<MULTI>(k[u], c), Kp), (uint32_t)(t + u));
+                        if (u < valid) cell(rk[u], t + (uint32_t)u);
                     t += HU;
                 });
-                x = L;
+                done = true;
             }
         }
-        // the rest of the band, then the end of every diagonal (rank Kp)
-        for (; x <= g.len0; ++x) {
-            uint32_t r = Kp;
-            if (x < g.len)
-                r = min(rho_of<MULTI>(__float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau)), rc), Kp);
-            cell(r, (uint32_t)x);
+        if (!done) {
+            for (int x = g.t0; x < g.t1; ++x) {
+                uint32_t r = Kp;
+                if (x < g.len)
+                    r = min(rho_of<MULTI>(__float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau)), rc),
+                            Kp);
+                cell(r, (uint32_t)x);
+            }
+        }
+        // trailing runs: below the last cell's rank empty, then one per stack entry
+        const uint32_t e = (uint32_t)g.t1;
+        #pragma unroll 1
+        for (uint32_t j = 0; j < min(top_r, Kp); ++j) lsuf[(size_t)j * TILE_W] = 0;
+        while (top_r <= Kp) {
+            const uint32_t hi = min(nx_r, Kp);
+            if (nx_r > Kp) {
+                // every cell of the segment recurrent at [top_r, Kp)
+                #pragma unroll 1
+                for (uint32_t j = top_r; j < hi; ++j) {
+                    lpre[(size_t)j * TILE_W] = (uint16_t)(e - t0);
+                    lsuf[(size_t)j * TILE_W] = (uint16_t)(e - t0);
+                }
+            } else {
+                #pragma unroll 1
+                for (uint32_t j = top_r; j < hi; ++j) lsuf[(size_t)j * TILE_W] = (uint16_t)(e - nx_p);
+            }
+            pop();
         }
     }
 };
 
 template <int NORM, int MC, int TC>
-__global__ void __launch_bounds__(HIST_BLOCK)
+__global__ void __launch_bounds__(1024)
 k_hist(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
        uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
-       uint64_t* __restrict__ dglob, uint32_t hist_len, uint32_t Kp)
+       uint64_t* __restrict__ dglob, uint16_t* __restrict__ pre, uint16_t* __restrict__ suf, uint32_t hist_len,
+       uint32_t Kp)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     HistBody<NORM, MC, TC> body;
     body.stab = (uint2*)smem;
     body.ses = (uint32_t*)(smem + RHO_TABLE * sizeof(uint2));
     body.stk = body.ses + RANK_MAX;
-    body.dsh = body.stk + (size_t)(Kp + 2) * HIST_BLOCK;
+    body.dsh = body.stk + (size_t)(Kp + 1) * blockDim.x;
+    body.sds = sds;
     body.rtab = rtab;
     body.works = works;
     body.dglob = dglob;
+    body.pre = pre;
+    body.suf = suf;
     body.hist_len = hist_len;
     body.kcap = Kp + 1;
+    body.chunk_tiles = chunk_tiles;
     body.multi = false;
-    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + hist_lds_bytes_dev(Kp)));
+    chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + hist_lds_bytes_dev(Kp, blockDim.x)));
 }
 
-size_t hist_lds_bytes(uint32_t Kp) { return hist_lds_bytes_dev(Kp) + 16; }
+// Lines across segment borders: thread (diagonal, threshold) walks the
+// diagonal's segments in order, carrying the run that reaches the segment's
+// end into the next segment's leading run (or through a segment recurrent
+// everywhere at that threshold).  A leading run of the first segment and a
+// trailing run of the last are lines too.  A workgroup (64 diagonals x 4
+// thresholds per step) strides over (band, threshold group) items and counts
+// short lines in LDS; one flush per workgroup.
+constexpr uint32_t HIST_JOIN_BLOCK = 256;
+
+__global__ void __launch_bounds__(HIST_JOIN_BLOCK)
+k_hist_join(const SeriesDesc* __restrict__ sds, const SeriesWork* __restrict__ works, uint32_t chunk_tiles,
+            const uint16_t* __restrict__ pre, const uint16_t* __restrict__ suf, uint64_t* __restrict__ dglob,
+            uint32_t hist_len, uint32_t kcap)
+{
+    __shared__ uint32_t cnt[HIST_SHORT * (HIST_MAX_K + 1)];
+    const uint32_t s = blockIdx.y;
+    const SeriesDesc& sd = sds[s];
+    const uint32_t Kp = works[s].Kp;
+    if (works[s].nonfinite) return;  // uniform over the workgroup
+    for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) cnt[i] = 0u;
+    __syncthreads();
+    uint64_t* dser = dglob + (size_t)s * hist_len * kcap;
+    const uint32_t jb = (Kp + 3) / 4;
+    const uint32_t lane = threadIdx.x % TILE_W;
+    const uint64_t B = sd.B, q = sd.q;
+    const uint32_t T = sd.T;
+    auto emit = [&](uint32_t l, uint32_t j) {
+        const uint32_t lb = min(l, hist_len - 1);
+        if (lb < HIST_SHORT) {
+            atomicAdd(&cnt[lb * kcap + j], 1u);
+        } else {
+            atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + j], 1ull);
+            atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + j + 1], ~0ull);
+        }
+    };
+    for (uint32_t item = blockIdx.x; item < sd.B * jb; item += gridDim.x) {
+        const uint32_t band = item / jb;
+        const uint32_t j = (item % jb) * 4 + threadIdx.x / TILE_W;
+        const uint32_t d = sd.w + band * TILE_W + lane;
+        if (j >= Kp || d >= sd.nv) continue;
+        const uint32_t len = sd.nv - d;
+        const uint32_t nseg = (len + T - 1) / T;
+        uint32_t carry = 0;
+        for (uint32_t g = 0; g < nseg; ++g) {
+            const uint64_t tile = (uint64_t)g * B - q * ((uint64_t)g * (g - 1) / 2) + band;
+            const size_t at = (((size_t)sd.chunk_begin * chunk_tiles + tile) * kcap + j) * TILE_W + lane;
+            const uint32_t seglen = min(T, len - g * T);
+            const uint32_t a = pre[at];
+            if (a == seglen) {
+                carry += seglen;
+            } else {
+                if (carry + a) emit(carry + a, j);
+                carry = suf[at];
+            }
+        }
+        if (carry) emit(carry, j);
+    }
+    __syncthreads();
+    // counts of one threshold: +c at j and -c at j + 1 of the difference rows
+    for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) {
+        const uint32_t c = cnt[i];
+        const uint32_t l = i / kcap, j = i % kcap;
+        if (c && l < hist_len) {
+            atomicAdd((unsigned long long*)&dser[(size_t)l * kcap + j], (unsigned long long)c);
+            atomicAdd((unsigned long long*)&dser[(size_t)l * kcap + j + 1], (unsigned long long)(-(int64_t)c));
+        }
+    }
+}
+
+size_t hist_lds_bytes(uint32_t Kp, uint32_t block) { return hist_lds_bytes_dev(Kp, block) + 16; }
 
 using HistFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint2*,
-                        uint64_t*, uint32_t, uint32_t);
+                        uint64_t*, uint16_t*, uint16_t*, uint32_t, uint32_t);
 
 template <int NORM>
 static HistFn hist_fn_n(int mclass)
@@ -1633,19 +1767,27 @@ static HistFn hist_fn(int select_variant)
     return norm == RQA_NORM_MAX ? hist_fn_n<RQA_NORM_MAX>(mc) : hist_fn_n<RQA_NORM_EUCLIDEAN>(mc);
 }
 
-hipError_t launch_hist(hipStream_t st, const DevBufs& b, int select_variant, uint32_t grid, uint64_t* dglob,
-                       uint32_t hist_len, uint32_t Kp, uint32_t ticket)
+hipError_t launch_hist(hipStream_t st, const DevBufs& b, int select_variant, uint32_t grid, uint32_t block,
+                       uint64_t* dglob, uint16_t* pre, uint16_t* suf, uint32_t hist_len, uint32_t Kp, uint32_t ticket)
 {
-    hipLaunchKernelGGL(hist_fn(select_variant), dim3(grid), dim3(HIST_BLOCK), hist_lds_bytes(Kp), st, b.sd, b.S,
-                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, dglob, hist_len, Kp);
+    hipLaunchKernelGGL(hist_fn(select_variant), dim3(grid), dim3(block), hist_lds_bytes(Kp, block), st, b.sd, b.S,
+                       b.nchunks, b.chunk_tiles, b.tickets + ticket, b.work, b.rtab, dglob, pre, suf, hist_len, Kp);
     return hipGetLastError();
 }
 
-int hist_blocks_per_cu(int select_variant, uint32_t Kp)
+hipError_t launch_hist_join(hipStream_t st, const DevBufs& b, uint32_t grid, const uint16_t* pre,
+                            const uint16_t* suf, uint64_t* dglob, uint32_t hist_len, uint32_t Kp)
+{
+    hipLaunchKernelGGL(k_hist_join, dim3(grid, b.S), dim3(HIST_JOIN_BLOCK), 0, st, b.sd, b.work, b.chunk_tiles, pre,
+                       suf, dglob, hist_len, Kp + 1);
+    return hipGetLastError();
+}
+
+int hist_blocks_per_cu(int select_variant, uint32_t Kp, uint32_t block)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hist_fn(select_variant), (int)HIST_BLOCK,
-                                                     hist_lds_bytes(Kp)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hist_fn(select_variant), (int)block,
+                                                     hist_lds_bytes(Kp, block)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

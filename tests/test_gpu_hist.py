@@ -121,13 +121,19 @@ def test_launch_shape_does_not_change_histogram(ctx):
     c = CASES[2]
     p = (c["m"], c["tau"], c["norm"], c["w"], c["lmin"])
     y = dev(c["y"])
-    ref = ctx.det_curve(y, p, c["eps"], hist_len=300)["hist"]
+    ref = oracle.lines(c["y"], c["m"], c["tau"], c["norm"], c["w"], c["lmin"], c["eps"], hist_len=300)["hist"]
     try:
         for g in (1, 3, 17):
             ctx.set_grid(g)
             assert np.array_equal(ctx.det_curve(y, p, c["eps"], hist_len=300)["hist"], ref), g
+        ctx.set_grid(0)
+        # segments from one tile wide to longer than every diagonal
+        for seg in (64, 128, 192, 640, 4096):
+            ctx.set_shape(segment=seg)
+            assert np.array_equal(ctx.det_curve(y, p, c["eps"], hist_len=300)["hist"], ref), seg
     finally:
         ctx.set_grid(0)
+        ctx.set_shape()
 
 
 def test_histogram_limits(ctx):
