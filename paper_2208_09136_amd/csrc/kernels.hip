@@ -1483,7 +1483,7 @@ struct HistBody {
     uint2* stab;          // LDS [RHO_TABLE]
     uint32_t* ses;        // LDS [RANK_MAX]
     uint32_t* stk;        // LDS [Kp + 1][blockDim] stack entries below the top two (column = thread)
-    uint32_t* dsh;        // LDS [HIST_SHORT][Kp + 1] difference counts of short lines
+    uint32_t* dsh;        // LDS [Kp + 1][HIST_SHORT] difference counts of short lines
     const SeriesDesc* sds;
     const uint2* rtab;
     SeriesWork* works;
@@ -1499,8 +1499,11 @@ struct HistBody {
     bool multi;
     bool active = true;
     // lane state: top (top_r, top_p) and next (nx_r, nx_p) of the stack; LDS rows
-    // [0, sp) hold the sentinel and then the entries below next (sp >= 1); pm is
-    // the largest rank so far in the segment
+    // [0, sp) hold the bottom sentinel and then the entries below next (sp >= 1);
+    // pm is the largest rank so far in the segment.  A cell of rank Kp ends every
+    // run: it replaces the whole stack as a new bottom sentinel (rank Kp + 1 at
+    // its position), so runs of such cells cost no pops.  Only the segment's own
+    // sentinel has position t0.
     uint32_t top_r, top_p, nx_r, nx_p, sp, pm, t0;
     uint16_t* lpre;       // this lane's pre / suf column in the current tile
     uint16_t* lsuf;
@@ -1526,7 +1529,7 @@ struct HistBody {
     __device__ __forceinline__ void flush(uint32_t)
     {
         for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) {
-            const uint32_t l = i / kcap, j = i % kcap;
+            const uint32_t j = i / HIST_SHORT, l = i % HIST_SHORT;
             const int32_t v = (int32_t)dsh[i];
             if (v && l < hist_len)
                 atomicAdd((unsigned long long*)&dser[(size_t)l * kcap + j], (unsigned long long)(int64_t)v);
@@ -1537,8 +1540,8 @@ struct HistBody {
     {
         const uint32_t lb = min(l, hist_len - 1);
         if (lb < HIST_SHORT) {
-            atomicAdd(&dsh[lb * kcap + a], 1u);
-            atomicAdd(&dsh[lb * kcap + b], 0xFFFFFFFFu);
+            atomicAdd(&dsh[a * HIST_SHORT + lb], 1u);
+            atomicAdd(&dsh[b * HIST_SHORT + lb], 0xFFFFFFFFu);
         } else {
             atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + a], 1ull);
             atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + b], ~0ull);
@@ -1549,7 +1552,7 @@ struct HistBody {
     {
         top_r = nx_r;
         top_p = nx_p;
-        // row 0 is the sentinel: below the sentinel is the sentinel again
+        // row 0 is the bottom sentinel: below it is the sentinel again
         const uint32_t e = row(sp - 1);
         nx_r = e >> 24;
         nx_p = e & 0xFFFFFFu;
@@ -1565,17 +1568,19 @@ struct HistBody {
             pm = r;
         }
         while (top_r <= r) {
-            // next is the sentinel: a leading run, recorded above
-            const uint32_t b = nx_r > rc.Kp ? top_r : min(nx_r, r);
+            // next is the segment's sentinel: a leading run, recorded above
+            const uint32_t b = nx_p == t0 ? top_r : min(nx_r, r);
             if (top_r < b) line(t - nx_p, top_r, b);
             pop();
         }
-        // a cell below the top: next goes to LDS (a sentinel next is row 0 already)
-        row(sp) = (nx_r << 24) | nx_p;
-        sp += nx_r <= rc.Kp ? 1u : 0u;
-        nx_r = top_r;
-        nx_p = top_p;
-        top_r = r;
+        const bool reset = r == rc.Kp;
+        const uint32_t snt = ((rc.Kp + 1) << 24) | (t + 1);
+        // push: a cell below the top sends next to LDS (a sentinel next is row 0 already)
+        row(reset ? 0u : sp) = reset ? snt : (nx_r << 24) | nx_p;
+        sp = reset ? 1u : sp + (nx_r <= rc.Kp ? 1u : 0u);
+        nx_r = reset ? rc.Kp + 1 : top_r;
+        nx_p = reset ? t + 1 : top_p;
+        top_r = reset ? rc.Kp + 1 : r;
         top_p = t + 1;
     }
     __device__ __forceinline__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
@@ -1634,7 +1639,7 @@ struct HistBody {
         for (uint32_t j = 0; j < min(top_r, Kp); ++j) lsuf[(size_t)j * TILE_W] = 0;
         while (top_r <= Kp) {
             const uint32_t hi = min(nx_r, Kp);
-            if (nx_r > Kp) {
+            if (nx_p == t0) {
                 // every cell of the segment recurrent at [top_r, Kp)
                 #pragma unroll 1
                 for (uint32_t j = top_r; j < hi; ++j) {
