@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--tune-file", default=None,
                     help="load launch shapes from this file if it exists, else tune and save them there")
     ap.add_argument("--no-bracket", action="store_true", help="skip the learned-bracket evaluation")
+    ap.add_argument("--no-hist", action="store_true", help="skip the full line-length histogram")
     ap.add_argument("--bracket-file", default=os.path.join(ROOT, "paper_2208_09136_amd", "bracket_params.npz"),
                     help="trained bracket network (written by paper_2208_09136_amd.bracket)")
     ap.add_argument("--bracket-series", type=int, default=200)
@@ -219,6 +220,8 @@ def main():
     k99 = {"ms_per_step": sec99 * 1e3, "value": sum(cells) * 99 / sec99, "unit": "cell-thresholds/s",
            "averaged_det_curve_end": [float(rqa.rqa_averaged_det(d)[-1]) for d in got99["det"]]}
 
+    full_hist = None if args.no_hist else bench_hist(ctx, torch, concat, offs, prm, out["eps"], args.steps)
+
     result = {
         "metric": METRIC, "value": value, "unit": "cell-thresholds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
@@ -234,6 +237,7 @@ def main():
         "roofline": roofline,
         "windowed_selection": windows,
         "k99": k99,
+        "full_histogram": full_hist,
         "det_mean": out["det_mean"].tolist(),
     }
 
@@ -257,6 +261,38 @@ def main():
 
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def bench_hist(ctx, torch, concat, offs, prm, eps, steps):
+    """Full diagonal line-length histogram P_r(l) (every length, hist_len =
+    nv + 1) at each series' selected thresholds: device time of the histogram
+    pass (segment pass + border join), and the identity sum_l l P_r(l) = C_r
+    against the sweep's counts."""
+    rows = []
+    for i, p in enumerate(prm):
+        y = concat[int(offs[i]):int(offs[i + 1])]
+        nv = int(offs[i + 1] - offs[i]) - (p[0] - 1) * p[1]
+        got = ctx.det_curve(y, p, eps[i], hist_len=nv + 1)
+        torch.cuda.synchronize()
+        hms = 0.0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            got = ctx.det_curve(y, p, eps[i], hist_len=nv + 1)
+            hms += ctx.phase_times()["histogram"]
+        wsec = (time.perf_counter() - t0) / steps
+        h = got["hist"].astype(np.int64)
+        lens = np.arange(h.shape[1], dtype=np.int64)
+        nz = np.nonzero(h.sum(axis=0))[0]
+        from paper_2208_09136_amd import rqa
+        L, lmax = rqa.rqa_line_measures(got["hist"], p[4])
+        rows.append({"histogram_ms": hms / steps, "call_ms": wsec * 1e3,
+                     "longest_line": int(nz.max()) if len(nz) else 0,
+                     "L_mean_over_thresholds": float(rqa.rqa_averaged_det(L)[-1]),
+                     "Lmax_mean_over_thresholds": float(lmax.astype(np.float64).mean()),
+                     "sum_l_P_equals_C": bool(np.array_equal((h * lens).sum(axis=1).astype(np.uint64),
+                                                             got["count"]))})
+    return {"workload": "each bench series at its 20 selected thresholds, every length kept",
+            "series": rows}
 
 
 def bench_batch(ctx, torch, rqa, reps=3):

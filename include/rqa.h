@@ -268,6 +268,22 @@ rqa_status rqa_set_grid(rqa_ctx *ctx, uint32_t workgroups);
  * device work.  Returns RQA_ERR_INVALID_ARG for NULL pointers or K = 0. */
 rqa_status rqa_averaged_det(const double *det, uint32_t K, double *curve_out);
 
+/* Average diagonal line length L and longest diagonal line L_max from line
+ * histograms (the histogram section of the GPU implementation derives DET,
+ * L and L_max from P(l); L and L_max follow the standard RQA definitions):
+ *   L_r = sum_{l >= lmin} l P_r(l) / sum_{l >= lmin} P_r(l), summed in
+ *         increasing l in double (NaN without a line of length >= lmin);
+ *   L_max_r = the largest l with P_r(l) > 0 (0 without a line).
+ * hist: K rows of hist_len entries as rqa_det_curve returns them (host).  A
+ * nonzero last entry counts as length hist_len - 1, so both are exact when
+ * hist_len exceeds the longest diagonal (nv - theiler + 1 entries or more).
+ * L_out[K], lmax_out[K] (host, either may be NULL).  Averaged forms over an
+ * RR set: rqa_averaged_det applied to L_out (the same running mean).
+ * Returns RQA_ERR_INVALID_ARG for hist NULL, K = 0, hist_len = 0 or
+ * lmin = 0.  No device work. */
+rqa_status rqa_line_measures(const uint64_t *hist, uint32_t K, uint64_t hist_len, uint32_t lmin,
+                             double *L_out, uint64_t *lmax_out);
+
 /* Human-readable name of a status code (static string). */
 const char *rqa_status_string(rqa_status s);
 

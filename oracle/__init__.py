@@ -180,5 +180,33 @@ def run(y, m, tau, norm, w, lmin, rr, method=0, hist_len=0):
     return out
 
 
+def line_measures(hist, lmin):
+    """Average diagonal line length L and longest line L_max per row of a line
+    histogram (rows P_r(l), l = 0 .. hist_len - 1; the last entry holds the
+    lines of that length or longer).  The paper derives DET, L and L_max from
+    the histogram (section on the GPU implementation) without printing the
+    last two; the standard RQA definitions are used:
+      L_r = sum_{l >= lmin} l P_r(l) / sum_{l >= lmin} P_r(l)  (NaN without
+            such a line), summed in increasing l in float64;
+      L_max_r = the largest l with P_r(l) > 0 (0 without a line).
+    Plain Python loops over the entries."""
+    hist = np.asarray(hist, dtype=np.uint64)
+    K, n = hist.shape
+    L = np.zeros(K, dtype=np.float64)
+    lmax = np.zeros(K, dtype=np.uint64)
+    for r in range(K):
+        num = 0
+        den = 0
+        for l in range(n):
+            c = int(hist[r, l])
+            if c:
+                lmax[r] = l
+            if l >= lmin:
+                num += l * c
+                den += c
+        L[r] = float(num) / float(den) if den else float("nan")
+    return L, lmax
+
+
 def num_threads():
     return int(_load().orc_num_threads())

@@ -1394,6 +1394,29 @@ rqa_status rqa_averaged_det(const double* det, uint32_t K, double* curve_out)
     return RQA_OK;
 }
 
+rqa_status rqa_line_measures(const uint64_t* hist, uint32_t K, uint64_t hist_len, uint32_t lmin, double* L_out,
+                             uint64_t* lmax_out)
+{
+    if (!hist || K == 0 || hist_len == 0 || lmin == 0)
+        return fail(RQA_ERR_INVALID_ARG, "hist is NULL, or K, hist_len or lmin is 0");
+    for (uint32_t r = 0; r < K; ++r) {
+        const uint64_t* row = hist + (size_t)r * hist_len;
+        double num = 0.0, den = 0.0;
+        uint64_t lmax = 0;
+        for (uint64_t l = 0; l < hist_len; ++l) {
+            if (!row[l]) continue;
+            lmax = l;
+            if (l >= lmin) {
+                num += (double)l * (double)row[l];
+                den += (double)row[l];
+            }
+        }
+        if (L_out) L_out[r] = den > 0.0 ? num / den : NAN;
+        if (lmax_out) lmax_out[r] = lmax;
+    }
+    return RQA_OK;
+}
+
 const char* rqa_status_string(rqa_status s)
 {
     switch (s) {

@@ -74,6 +74,7 @@ SIGNATURES = {
     "rqa_set_sample_width": (_i32, [_vp, ctypes.c_float]),
     "rqa_selection_stats": (_i32, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "rqa_averaged_det": (_i32, [_dp, _u32, _dp]),
+    "rqa_line_measures": (_i32, [_up, _u32, _u64, _u32, _dp, _up]),
     "rqa_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_tune_load": (_i32, [_vp, ctypes.c_char_p]),
     "rqa_status_string": (ctypes.c_char_p, [_i32]),
@@ -292,6 +293,19 @@ def rqa_averaged_det(det):
     out = np.zeros(d.size, np.float64)
     _check(load().rqa_averaged_det(_p(d, ctypes.c_double), d.size, _p(out, ctypes.c_double)))
     return out
+
+
+def rqa_line_measures(hist, lmin):
+    """(L, L_max) per row of a (K, hist_len) line histogram, in the library."""
+    h = _a(hist, np.uint64)
+    if h.ndim != 2:
+        raise ValueError("hist must be (K, hist_len)")
+    K, n = h.shape
+    L = np.zeros(K, np.float64)
+    lmax = np.zeros(K, np.uint64)
+    _check(load().rqa_line_measures(_p(h, ctypes.c_uint64), K, n, lmin, _p(L, ctypes.c_double),
+                                    _p(lmax, ctypes.c_uint64)))
+    return L, lmax
 
 
 def rqa_tune_save(ctx, path):

@@ -69,3 +69,27 @@ def test_averaged_det_curve_host_function():
     assert nan[0] == 0.5 and np.isnan(nan[1]) and np.isnan(nan[2])
     with pytest.raises(rqa.RqaError):
         rqa.rqa_averaged_det([])
+
+
+def test_line_measures_host_function():
+    # host-only entry point: L and L_max from histograms, equal to the oracle's
+    import oracle
+    import synth
+    h = np.array([[0, 3, 0, 2, 0, 1], [0, 4, 0, 0, 0, 0], [0] * 6], dtype=np.uint64)
+    L, lmax = rqa.rqa_line_measures(h, 2)
+    assert L[0] == 11 / 3 and np.isnan(L[1]) and np.isnan(L[2])
+    assert lmax.tolist() == [5, 1, 0]
+    c = synth.config_small(2)
+    nv = len(c["y"])
+    eps = oracle.select(c["y"], 1, 1, 0, 1, c["rr"])[0]
+    for hl, lmin in ((nv + 1, 2), (12, 2), (nv + 1, 5), (3, 1)):
+        hist = oracle.lines(c["y"], 1, 1, 0, 1, lmin, eps, hist_len=hl)["hist"]
+        got = rqa.rqa_line_measures(hist, lmin)
+        want = oracle.line_measures(hist, lmin)
+        np.testing.assert_array_equal(got[0], want[0])
+        np.testing.assert_array_equal(got[1], want[1])
+    for bad in (np.zeros((0, 4), np.uint64), np.zeros((2, 0), np.uint64)):
+        with pytest.raises(rqa.RqaError):
+            rqa.rqa_line_measures(bad, 2)
+    with pytest.raises(rqa.RqaError):
+        rqa.rqa_line_measures(h, 0)

@@ -86,6 +86,10 @@ def test_histogram_equals_oracle(ctx, idx):
         want = oracle.lines(c["y"], c["m"], c["tau"], c["norm"], c["w"], c["lmin"], c["eps"], hist_len=hl)
         assert got["hist"].shape == (len(c["eps"]), hl)
         assert np.array_equal(got["hist"], want["hist"]), hl
+        from paper_2208_09136_amd import rqa
+        gl, gm = rqa.rqa_line_measures(got["hist"], c["lmin"])
+        wl, wm = oracle.line_measures(want["hist"], c["lmin"])
+        assert np.array_equal(gl, wl, equal_nan=True) and np.array_equal(gm, wm)
         # the other outputs do not change with the histogram
         for key in ("count", "rr"):
             assert np.array_equal(got[key], plain[key]), key

@@ -322,3 +322,57 @@ def test_error_paths():
     with pytest.raises(oracle.OracleError) as e:
         oracle.select(y, 1, 1, 0, 1, [0.0])
     assert e.value.status == oracle.ERR_INVALID
+
+
+# ------------------------------------------------------- L and L_max from P(l)
+def np_line_lengths(y, m, tau, norm, w, eps):
+    """Every diagonal line's length, from the explicit boolean matrix."""
+    R = np_key_matrix(y, m, tau, norm) <= np.float32(eps)
+    out = []
+    for d in range(w, R.shape[0]):
+        diag = np.concatenate([[False], np.diagonal(R, offset=d), [False]]).astype(np.int8)
+        edges = np.diff(diag)
+        out += (np.flatnonzero(edges == -1) - np.flatnonzero(edges == 1)).tolist()
+    return out
+
+
+def test_line_measures_literal_example():
+    # P = (0, 3, 0, 2, 0, 1): lines 1,1,1,3,3,5
+    h = np.array([[0, 3, 0, 2, 0, 1], [0, 4, 0, 0, 0, 0], [0] * 6], dtype=np.uint64)
+    L, lmax = oracle.line_measures(h, 2)
+    assert L[0] == 11 / 3 and lmax[0] == 5
+    assert math.isnan(L[1]) and lmax[1] == 1
+    assert math.isnan(L[2]) and lmax[2] == 0
+    L1, _ = oracle.line_measures(h, 1)
+    assert L1[0] == 14 / 6 and L1[1] == 1.0
+
+
+@pytest.mark.parametrize("m,tau,norm,w,lmin", [(1, 1, 0, 1, 2), (3, 5, 1, 1, 2), (2, 3, 0, 2, 3)])
+def test_line_measures_brute_force(m, tau, norm, w, lmin):
+    # mean length of the lines of at least lmin, and the longest line, taken
+    # directly from the run lengths of the boolean matrix
+    y = rng(12).standard_normal(150).astype(np.float32)
+    keys = np.sort(np_keys_diag_major(y, m, tau, norm, w))
+    eps = [keys[len(keys) // 40], keys[len(keys) // 5], keys[len(keys) // 2]]
+    nv = oracle.num_vectors(len(y), m, tau)
+    out = oracle.lines(y, m, tau, norm, w, lmin, eps, hist_len=nv + 1)
+    L, lmax = oracle.line_measures(out["hist"], lmin)
+    for r, e in enumerate(eps):
+        ls = np_line_lengths(y, m, tau, norm, w, e)
+        long_ = [l for l in ls if l >= lmin]
+        assert lmax[r] == max(ls)
+        if long_:
+            assert L[r] == pytest.approx(sum(long_) / len(long_), rel=1e-15)
+        else:
+            assert math.isnan(L[r])
+
+
+def test_line_measures_periodic_closed_form():
+    # y_t = c_{t mod P}: at eps = 0 the lines are the whole diagonals d = P, 2P, ...
+    for n, P in [(400, 7), (333, 10)]:
+        y = synth.periodic_integer(n, P)
+        out = oracle.lines(y, 1, 1, 0, 1, 2, [0.0], hist_len=n + 1)
+        L, lmax = oracle.line_measures(out["hist"], 2)
+        lens = [n - d for d in range(P, n, P) if n - d >= 2]
+        assert lmax[0] == n - P
+        assert L[0] == pytest.approx(sum(lens) / len(lens), rel=1e-15)
