@@ -622,10 +622,44 @@ int select_blocks_per_cu(int pass, int variant, uint32_t block, size_t lds)
 
 // ------------------------------------------------------------------ scans
 
+// Exclusive prefix over the workgroup of one u64 per thread (blockDim.x a
+// multiple of 64, at most 1024): shuffles inside each wave, then the wave
+// totals.  *total receives the sum over the workgroup.  Called by every
+// thread.
+__device__ uint64_t block_excl_scan(uint64_t v, uint64_t* total)
+{
+    __shared__ uint64_t wsum[16];
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+    for (uint32_t i = 0; i < nw; ++i) {
+        const uint64_t t = wsum[i];
+        base += i < wid ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+// Sum over the workgroup of one u64 per thread (every thread gets it).
+__device__ __forceinline__ uint64_t block_sum(uint64_t v)
+{
+    uint64_t tot;
+    (void)block_excl_scan(v, &tot);
+    return tot;
+}
+
 // Inclusive prefix sums of n (multiple of blockDim.x) u64 values into LDS.
 __device__ void block_cumsum(const uint64_t* __restrict__ src, uint64_t* cum, uint32_t n)
 {
-    __shared__ uint64_t part[1024];
     const uint32_t per = n / blockDim.x;
     const uint32_t base = threadIdx.x * per;
     uint64_t s = 0;
@@ -633,20 +667,47 @@ __device__ void block_cumsum(const uint64_t* __restrict__ src, uint64_t* cum, ui
         s += src[base + i];
         cum[base + i] = s;
     }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (uint32_t t = 0; t < blockDim.x; ++t) {
-            const uint64_t v = part[t];
-            part[t] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    const uint64_t off = part[threadIdx.x];
+    uint64_t tot;
+    const uint64_t off = block_excl_scan(s, &tot);
     for (uint32_t i = 0; i < per; ++i) cum[base + i] += off;
     __syncthreads();
+}
+
+// Prefix sums of n u64 counts, one chunk of ceil(n / blockDim.x) per thread:
+// pre[t] = sum of the chunks before thread t's, pre[blockDim.x] = the total.
+// Then first_in_chunks finds, for one count kk <= total, the first index
+// whose inclusive prefix reaches kk (binary search over the chunk prefixes,
+// then a walk of one chunk), with the sum before it.
+__device__ void chunk_prefix(const uint64_t* __restrict__ c, uint32_t n, uint64_t* pre /* LDS [blockDim.x + 1] */)
+{
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
+    uint64_t sum = 0;
+    for (uint32_t i = b0; i < b1; ++i) sum += c[i];
+    uint64_t tot;
+    pre[threadIdx.x] = block_excl_scan(sum, &tot);
+    if (threadIdx.x == 0) pre[blockDim.x] = tot;
+    __syncthreads();
+}
+
+__device__ uint32_t first_in_chunks(const uint64_t* __restrict__ c, uint32_t n, const uint64_t* pre, uint64_t kk,
+                                    uint64_t* before)
+{
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    uint32_t lo = 0, hi = blockDim.x;  // pre[lo] < kk <= pre[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] < kk) lo = mid; else hi = mid;
+    }
+    uint64_t run = pre[lo];
+    const uint32_t b1 = min(lo * per + per, n);
+    uint32_t i = lo * per;
+    for (; i + 1 < b1; ++i) {
+        if (run + c[i] >= kk) break;
+        run += c[i];
+    }
+    *before = run;
+    return i;
 }
 
 // First index i in [0, n) with cum[i] >= k (cum inclusive, nondecreasing);
@@ -1948,37 +2009,50 @@ __global__ void __launch_bounds__(256) k_range_scan(const SeriesDesc* __restrict
                                                     const uint64_t* __restrict__ fineK,
                                                     const uint64_t* __restrict__ fineL, uint32_t fine_stride)
 {
-    const uint32_t s = blockIdx.x;
-    const uint32_t K = sds[s].K;
+    // workgroup (series, target)
+    __shared__ uint64_t pre[257];
+    __shared__ uint32_t s_c;
+    __shared__ uint64_t s_run;
+    const uint32_t s = blockIdx.x, r = blockIdx.y;
     SeriesWork& w = works[s];
-    if (!w.range_ok) return;
+    if (r >= sds[s].K || !w.range_ok) return;  // uniform over the workgroup
     const uint32_t bits = w.range_bits, width = 1u << bits;
     const uint64_t* fk = fineK + (size_t)s * fine_stride;
     const uint64_t* fl = fineL + (size_t)s * fine_stride;
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
-        const uint32_t j = w.t_sub[r], gi = w.t_group[r];
-        const uint32_t f0 = w.g_off[gi], fj = j << bits;
-        uint64_t cl = 0;
-        for (uint32_t row = 0; row < 2 * gi + 1; ++row) cl += w.hlam[row];
-        for (uint32_t i = f0; i < fj; ++i) cl += fl[i];
-        const uint64_t want = w.k[r] - w.rbase[r];
-        uint64_t run = 0;
-        uint32_t c = 0;
-        for (; c < width; ++c) {
-            if (run + fk[fj + c] >= want) break;
-            run += fk[fj + c];
+    const uint32_t j = w.t_sub[r], gi = w.t_group[r];
+    const uint32_t f0 = w.g_off[gi], fj = j << bits;
+    // line values below the target's fine range: line-rank rows and fine bins
+    uint64_t part = 0;
+    for (uint32_t row = threadIdx.x; row < 2 * gi + 1; row += blockDim.x) part += w.hlam[row];
+    for (uint32_t i = f0 + threadIdx.x; i < fj; i += blockDim.x) part += fl[i];
+    // the target's fine bin: first c with rbase + keys up to bin c >= k
+    const uint64_t want = w.k[r] - w.rbase[r];
+    chunk_prefix(fk + fj, width, pre);
+    if (threadIdx.x == 0) {
+        if (pre[blockDim.x] >= want) {
+            uint64_t before;
+            s_c = first_in_chunks(fk + fj, width, pre, want, &before);
+            s_run = before;
+        } else {
+            s_c = width - 1;
+            s_run = pre[blockDim.x];
+            atomicOr(&w.status, 32u);
         }
-        if (c == width) { c = width - 1; atomicOr(&w.status, 32u); }
-        for (uint32_t i = 0; i <= c; ++i) cl += fl[fj + i];
+    }
+    __syncthreads();
+    const uint32_t c = s_c;
+    for (uint32_t i = threadIdx.x; i <= c; i += blockDim.x) part += fl[fj + i];
+    const uint64_t cl = block_sum(part);
+    if (threadIdx.x == 0) {
         w.eps_bits[r] = w.sub_lo[j] + c;
-        w.count[r] = w.rbase[r] + run + fk[fj + c];
+        w.count[r] = w.rbase[r] + s_run + fk[fj + c];
         w.dcount[r] = cl;
     }
 }
 
 hipError_t launch_range_scan(hipStream_t st, const DevBufs& b)
 {
-    hipLaunchKernelGGL(k_range_scan, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.fineK, b.fineL, b.fine_stride);
+    hipLaunchKernelGGL(k_range_scan, dim3(b.S, b.K), dim3(256), 0, st, b.sd, b.work, b.fineK, b.fineL, b.fine_stride);
     return hipGetLastError();
 }
 
@@ -2235,51 +2309,13 @@ int window_blocks_per_cu(int pass, int variant, uint32_t block)
     return n > 0 ? n : 1;
 }
 
-// Block-cooperative search over n counts: the first index whose inclusive
-// prefix sum reaches kk (1 <= kk <= total); before = the prefix sum below it.
-// Returns false if the counts total less than kk.  All threads must call it.
-__device__ bool block_find(const uint64_t* __restrict__ c, uint32_t n, uint64_t kk, uint32_t* idx, uint64_t* before,
-                           uint64_t* part /* LDS [blockDim.x + 1] */)
-{
-    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
-    const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
-    uint64_t sum = 0;
-    for (uint32_t i = b0; i < b1; ++i) sum += c[i];
-    part[threadIdx.x + 1] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        part[0] = 0;
-        for (uint32_t t = 1; t <= blockDim.x; ++t) part[t] += part[t - 1];
-    }
-    __syncthreads();
-    const bool ok = part[blockDim.x] >= kk;
-    bool found = false;
-    if (ok && part[threadIdx.x] < kk && part[threadIdx.x + 1] >= kk) {
-        uint64_t run = part[threadIdx.x];
-        for (uint32_t i = b0; i < b1; ++i) {
-            if (run + c[i] >= kk) {
-                *idx = i;
-                *before = run;
-                found = true;
-                break;
-            }
-            run += c[i];
-        }
-    }
-    (void)found;
-    __syncthreads();
-    return ok;
-}
-
 // After window pass 1: per target, hit if its rank falls inside the window;
 // its fine bin and the count below that bin; pass-2 slots and table.
 __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
                                                       uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
                                                       uint64_t* __restrict__ fine, uint32_t clear_fine)
 {
-    __shared__ uint64_t part[257];
-    __shared__ uint32_t s_idx;
-    __shared__ uint64_t s_before;
+    __shared__ uint64_t pre[257];
     __shared__ uint32_t uniq[RQA_MAX_K];
     __shared__ uint32_t nuniq;
     const uint32_t s = blockIdx.x;
@@ -2290,22 +2326,19 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
     const bool ok = w.win_ok != 0;
     const uint64_t below = w.win_below;
     const uint64_t* cb = bins + (size_t)s * WIN_BINS;
-    for (uint32_t r = 0; r < K; ++r) {
+    chunk_prefix(cb, WIN_BINS, pre);
+    const uint64_t total = pre[blockDim.x];
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
         const uint64_t k = w.k[r];
-        bool hit = ok && k > below;
+        const bool hit = ok && k > below && k - below <= total;
+        w.win_hit[r] = hit ? 1u : 0u;
         if (hit) {
-            hit = block_find(cb, WIN_BINS, k - below, &s_idx, &s_before, part);
-            __syncthreads();
+            uint64_t before;
+            w.win_fbin[r] = first_in_chunks(cb, WIN_BINS, pre, k - below, &before);
+            w.win_base[r] = below + before;
         }
-        if (threadIdx.x == 0) {
-            w.win_hit[r] = hit ? 1u : 0u;
-            if (hit) {
-                w.win_fbin[r] = s_idx;
-                w.win_base[r] = below + s_before;
-            }
-        }
-        __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t n = 0;
         for (uint32_t r = 0; r < K; ++r)
@@ -2333,27 +2366,26 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
 __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
                                                       const uint64_t* __restrict__ fine)
 {
-    __shared__ uint64_t part[257];
-    __shared__ uint32_t s_idx;
-    __shared__ uint64_t s_before;
-    const uint32_t s = blockIdx.x;
+    // workgroup (series, target)
+    __shared__ uint64_t pre[257];
+    const uint32_t s = blockIdx.x, r = blockIdx.y;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
+    if (r >= K || !w.win_hit[r]) return;  // uniform over the workgroup
     const uint32_t nsub = 1u << w.win_shift;
-    for (uint32_t r = 0; r < K; ++r) {
-        if (!w.win_hit[r]) continue;
-        const uint64_t* c = fine + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT);
-        const bool ok = block_find(c, nsub, w.k[r] - w.win_base[r], &s_idx, &s_before, part);
-        if (threadIdx.x == 0) {
-            if (ok) {
-                w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + s_idx;
-                w.count[r] = w.win_base[r] + s_before + c[s_idx];
-            } else {
-                w.win_hit[r] = 0u;
-                atomicOr(&w.status, 8u);
-            }
+    const uint64_t* c = fine + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT);
+    const uint64_t want = w.k[r] - w.win_base[r];
+    chunk_prefix(c, nsub, pre);
+    if (threadIdx.x == 0) {
+        if (pre[blockDim.x] >= want) {
+            uint64_t before;
+            const uint32_t idx = first_in_chunks(c, nsub, pre, want, &before);
+            w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + idx;
+            w.count[r] = w.win_base[r] + before + c[idx];
+        } else {
+            w.win_hit[r] = 0u;
+            atomicOr(&w.status, 8u);
         }
-        __syncthreads();
     }
 }
 
@@ -2364,7 +2396,7 @@ hipError_t launch_window_scan(hipStream_t st, const DevBufs& b, const WinBufs& w
     if (pass == 1)
         hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.bins, w.table, w.fine,
                            w.fine ? 1u : 0u);
-    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.fine);
+    else hipLaunchKernelGGL(k_window_scan2, dim3(b.S, b.K), dim3(256), 0, st, b.sd, b.work, w.fine);
     return hipGetLastError();
 }
 
