@@ -1324,8 +1324,12 @@ k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32
     chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + sweep_lds_bytes_dev(Kcap, false)));
 }
 
+// Six waves per SIMD (three workgroups of 512 per CU, which the LDS allows up
+// to K = 40 or so): the register budget drops to 80 and a few spill, but the
+// extra waves hide the rank-table and series loads better (about 10% faster
+// at K = 20 than the four waves 105 registers allow).
 template <int NORM, int MC, int TC, int LMC>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
 k_range_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
               uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab,
               uint32_t rows, uint64_t* __restrict__ fineK, uint64_t* __restrict__ fineL, uint32_t fine_stride)
