@@ -65,6 +65,8 @@ def parse():
                     help="load launch shapes from this file if it exists, else tune and save them there")
     ap.add_argument("--no-bracket", action="store_true", help="skip the learned-bracket evaluation")
     ap.add_argument("--no-hist", action="store_true", help="skip the full line-length histogram")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the plain step only (no windowed selection, K = 99 or histogram lines)")
     ap.add_argument("--bracket-file", default=os.path.join(ROOT, "paper_2208_09136_amd", "bracket_params.npz"),
                     help="trained bracket network (written by paper_2208_09136_amd.bracket)")
     ap.add_argument("--bracket-series", type=int, default=200)
@@ -191,7 +193,7 @@ def main():
     if have_net:
         bracket.load(ctx, args.bracket_file)
     for name, flags in (("sample", rqa.RQA_SEL_SAMPLE), ("network", rqa.RQA_SEL_LEARNED)):
-        if name == "network" and not have_net:
+        if args.no_extras or (name == "network" and not have_net):
             continue
         got = ctx.batch(concat, offs, prm, rr, flags=flags)
         torch.cuda.synchronize()
@@ -208,19 +210,10 @@ def main():
                          "identical": bool(all(np.array_equal(got[k], out[k]) for k in ("eps", "count", "det"))),
                          "speedup_vs_plain": sec / wsec}
 
-    # the paper's RR set 1..99 % on the same series (averaged-DET curve over RR*)
-    rr99 = np.tile(np.array([k / 100.0 for k in range(1, 100)]), (len(cases), 1))
-    got99 = ctx.batch(concat, offs, prm, rr99)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        got99 = ctx.batch(concat, offs, prm, rr99)
-    torch.cuda.synchronize()
-    sec99 = (time.perf_counter() - t0) / args.steps
-    k99 = {"ms_per_step": sec99 * 1e3, "value": sum(cells) * 99 / sec99, "unit": "cell-thresholds/s",
-           "averaged_det_curve_end": [float(rqa.rqa_averaged_det(d)[-1]) for d in got99["det"]]}
-
-    full_hist = None if args.no_hist else bench_hist(ctx, torch, concat, offs, prm, out["eps"], args.steps)
+    k99 = None if args.no_extras else bench_k99(ctx, torch, rqa, concat, offs, prm, len(cases), sum(cells),
+                                                 args.steps)
+    full_hist = None if (args.no_hist or args.no_extras) else bench_hist(ctx, torch, concat, offs, prm, out["eps"],
+                                                                          args.steps)
 
     result = {
         "metric": METRIC, "value": value, "unit": "cell-thresholds/s", "n_gpus": 1,
@@ -261,6 +254,20 @@ def main():
 
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def bench_k99(ctx, torch, rqa, concat, offs, prm, nseries, cells, steps):
+    """The paper's RR set 1..99 % on the bench series (averaged-DET curve over RR*)."""
+    rr99 = np.tile(np.array([k / 100.0 for k in range(1, 100)]), (nseries, 1))
+    got99 = ctx.batch(concat, offs, prm, rr99)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        got99 = ctx.batch(concat, offs, prm, rr99)
+    torch.cuda.synchronize()
+    sec99 = (time.perf_counter() - t0) / steps
+    return {"ms_per_step": sec99 * 1e3, "value": cells * 99 / sec99, "unit": "cell-thresholds/s",
+            "averaged_det_curve_end": [float(rqa.rqa_averaged_det(d)[-1]) for d in got99["det"]]}
 
 
 def bench_hist(ctx, torch, concat, offs, prm, eps, steps):
