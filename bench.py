@@ -214,6 +214,7 @@ def main():
                                                  args.steps)
     full_hist = None if (args.no_hist or args.no_extras) else bench_hist(ctx, torch, concat, offs, prm, out["eps"],
                                                                           args.steps)
+    sorting = None if args.no_extras else bench_sorting(ctx)
 
     result = {
         "metric": METRIC, "value": value, "unit": "cell-thresholds/s", "n_gpus": 1,
@@ -231,6 +232,7 @@ def main():
         "windowed_selection": windows,
         "k99": k99,
         "full_histogram": full_hist,
+        "sorting_rate": sorting,
         "det_mean": out["det_mean"].tolist(),
     }
 
@@ -268,6 +270,46 @@ def bench_k99(ctx, torch, rqa, concat, offs, prm, nseries, cells, steps):
     sec99 = (time.perf_counter() - t0) / steps
     return {"ms_per_step": sec99 * 1e3, "value": cells * 99 / sec99, "unit": "cell-thresholds/s",
             "averaged_det_curve_end": [float(rqa.rqa_averaged_det(d)[-1]) for d in got99["det"]]}
+
+
+def bench_sorting(ctx, lengths=(100, 1000, 10_000), grid_realisations=1):
+    """Sorting rate S (Eq. 5) of the paper's ensemble (sine of 25 cycles,
+    logistic r = 3.679, Lorenz-x; linear SNR levels 0.1, 1, 10; 10 SNRs x 10
+    realisations per cell; maximum norm, m = 1 or m = 3 / tau = 3 for
+    Lorenz) ordered by the averaged DET over RR* = 1..99 % and by DET at
+    RR = 1 %, and the grid-threshold variant's RR error against exact
+    selection on one realisation per cell."""
+    from paper_2208_09136_amd import harness
+    t0 = time.perf_counter()
+    table, gerr, eerr = [], [], []
+    gpu = 0.0
+    for system in synth.SYSTEMS:
+        m, tau = synth.paper_embedding(system)
+        params = (m, tau, 0, 1, 2)
+        for level in synth.SNR_LEVELS:
+            for n in lengths:
+                ens = synth.paper_ensemble(system, n, level)
+                t1 = time.perf_counter()
+                avg, first = harness.ensemble_measures(ctx, ens, params)
+                gpu += time.perf_counter() - t1
+                table.append({"system": system, "snr_level": level, "n": n,
+                              "S_det_avg_99_pct": harness.sorting_rate(avg),
+                              "S_det_1_pct": harness.sorting_rate(first)})
+                for r in range(grid_realisations):
+                    for y in ens[r]:
+                        g, e = harness.grid_vs_exact(ctx, y, params)
+                        gerr.append(g)
+                        eerr.append(e)
+    gerr, eerr = np.concatenate(gerr), np.concatenate(eerr)
+    wins = sum(1 for row in table if row["S_det_avg_99_pct"] > row["S_det_1_pct"])
+    ties = sum(1 for row in table if row["S_det_avg_99_pct"] == row["S_det_1_pct"])
+    return {"workload": f"{len(table)} cells x 100 series, lengths {list(lengths)}, K = 99 per series",
+            "table": table, "cells_avg_better": wins, "cells_equal": ties,
+            "batch_seconds": gpu, "seconds": time.perf_counter() - t0,
+            "grid_variant": {"targets": int(gerr.size),
+                             "grid_rr_error_pct": {"mean": 100 * float(gerr.mean()), "max": 100 * float(gerr.max())},
+                             "exact_rr_error_pct": {"mean": 100 * float(eerr.mean()),
+                                                    "max": 100 * float(eerr.max())}}}
 
 
 def bench_hist(ctx, torch, concat, offs, prm, eps, steps):

@@ -208,5 +208,63 @@ def line_measures(hist, lmin):
     return L, lmax
 
 
+def sorting_rate(measure):
+    """Sorting rate S of Eq. 5 in percent.  measure[i][j] is the measure of
+    realisation i's series of SNR index j (SNRs ascending).  x_j is the
+    position (1-based) of series j when realisation i's series are ordered by
+    ascending measure (equal values keep their SNR order; NaN after every
+    number), y_j = j and z the reversed y:
+      S = 100 (sum_i sum_j |z_j - y_j| - sum_i sum_j |x_j - y_j|)
+              / sum_i sum_j |z_j - y_j|.
+    Plain loops: the position of series j counts the series before it."""
+    def before(a, ka, b, kb):
+        # does (value a, index ka) sort before (value b, index kb)?
+        na, nb = a != a, b != b
+        if na != nb:
+            return nb
+        if not na and a != b:
+            return a < b
+        return ka < kb
+    worst = 0
+    dep = 0
+    for row in measure:
+        n = len(row)
+        for j in range(n):
+            pos = 1 + sum(1 for k in range(n) if k != j and before(float(row[k]), k, float(row[j]), j))
+            dep += abs(pos - (j + 1))
+            worst += abs((n - j) - (j + 1))
+    return 100.0 * (worst - dep) / worst
+
+
+def grid_select(y, m, tau, norm, w, targets, n_grid=400):
+    """The grid-threshold variant (a commented-out paragraph of the Averaged
+    RQA section): y rescaled to [0, 1] (float64, then float32), RR at the
+    thresholds i / n_grid (i = 1..n_grid; squared for the Euclidean key),
+    and per target the grid threshold whose RR is closest (the first on
+    ties).  Returns (eps, rr, |rr - target|) per target."""
+    y = np.asarray(y, dtype=np.float64)
+    lo, hi = float(y.min()), float(y.max())
+    y01 = ((y - lo) / (hi - lo)).astype(np.float32)
+    grid = []
+    for i in range(1, n_grid + 1):
+        e = i / n_grid
+        grid.append(e if norm == NORM_MAX else e * e)
+    grid = np.array(grid, dtype=np.float32)
+    _, le = count(y01, m, tau, norm, w, grid)
+    M = num_pairs(num_vectors(len(y01), m, tau), w)
+    rr = [int(c) / M for c in le]
+    eps_out, rr_out, err = [], [], []
+    for t in targets:
+        best = 0
+        for i in range(1, len(rr)):
+            if abs(rr[i] - t) < abs(rr[best] - t):
+                best = i
+        eps_out.append(grid[best])
+        rr_out.append(rr[best])
+        err.append(abs(rr[best] - t))
+    return (np.array(eps_out, dtype=np.float32), np.array(rr_out, dtype=np.float64),
+            np.array(err, dtype=np.float64))
+
+
 def num_threads():
     return int(_load().orc_num_threads())

@@ -329,3 +329,57 @@ def bracket_set(count, seed, lo=1000, hi=100_000, snr_lo=-25.0, snr_hi=20.0, m=N
     offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint64)
     params = [(int(mm), 5 if mm == 3 else 1, NORM_EUCLID, 1, 2) for mm in ms]
     return np.concatenate(ys), offs, params, systems, snrs
+
+
+# ---------------------------------------------------------------------------
+# The sorting-rate ensemble of the Methodology section: for each system, SNR
+# level and length, 10 equidistant SNRs (a linear variance ratio) x R noise
+# realisations.  The periodic signal is a sine of 25 cycles over the series
+# (the paper's light-curve generator set to equidistant sine sampling with 25
+# observed cycles), the logistic map uses r = 3.679 (band merging), the
+# Lorenz x-component the same integration as above.
+
+SNR_LEVELS = {
+    "0.1": tuple(k / 100.0 for k in range(1, 11)),   # 0.01, 0.02, ..., 0.1
+    "1": tuple(k / 10.0 for k in range(1, 11)),      # 0.1, 0.2, ..., 1
+    "10": tuple(float(k) for k in range(1, 11)),     # 1, 2, ..., 10
+}
+PAPER_LOGISTIC_R = 3.679
+PAPER_SINE_CYCLES = 25
+
+
+def paper_embedding(system):
+    """(m, tau) of the sorting-rate experiments: m = 3, tau = 3 for Lorenz
+    (the values the paper gives); m = 1 otherwise."""
+    return (3, 3) if system == "lorenz" else (1, 1)
+
+
+def paper_ensemble(system, n, level, realisations=10, seed=0):
+    """Series of one (system, length, SNR level) cell of the sorting-rate
+    ensemble: a list over realisations of lists over the 10 SNRs (ascending)
+    of float32 series of length n.  Each realisation draws its own clean
+    signal (initial condition or phase) and noise, from the key (seed,
+    system, level, n)."""
+    snrs = SNR_LEVELS[level]
+    si = SYSTEMS.index(system)
+    li = list(SNR_LEVELS).index(level)
+    rng = rng_for(7, seed, si, li, int(n))
+    count = realisations * len(snrs)
+    lengths = np.full(count, int(n), dtype=np.int64)
+    if system == "sine":
+        clean_ = [sine(int(n), rng, period=n / PAPER_SINE_CYCLES) for _ in range(count)]
+    elif system == "logistic":
+        clean_ = _logistic_many(lengths, rng, r=PAPER_LOGISTIC_R)
+    else:
+        clean_ = _lorenz_many(lengths, rng)
+    out = []
+    for r in range(realisations):
+        row = []
+        for q, snr in enumerate(snrs):
+            c = clean_[r * len(snrs) + q]
+            y = add_noise(c, 10.0 * math.log10(snr), rng).astype(np.float32)
+            if not np.all(np.isfinite(y)) or float(np.std(y)) <= 0.0:
+                raise RuntimeError(f"degenerate synthetic series {system} {n} {level}")
+            row.append(y)
+        out.append(row)
+    return out

@@ -59,3 +59,4 @@ def test_targets_are_bit_offsets():
     eps = np.array([[1.0, 2.0, 0.5]], np.float32)
     scale = np.array([np.float32(1.0).view(np.uint32)], np.uint32)
     assert np.array_equal(bracket.targets(eps, scale), [[0.0, 1.0, -1.0]])
+

@@ -376,3 +376,42 @@ def test_line_measures_periodic_closed_form():
         lens = [n - d for d in range(P, n, P) if n - d >= 2]
         assert lmax[0] == n - P
         assert L[0] == pytest.approx(sum(lens) / len(lens), rel=1e-15)
+
+
+# ------------------------------------------------------- sorting rate (Eq. 5)
+def test_sorting_rate_closed_forms():
+    perfect = [list(range(10)) for _ in range(10)]
+    assert oracle.sorting_rate(perfect) == 100.0
+    reversed_ = [list(range(10, 0, -1)) for _ in range(10)]
+    assert oracle.sorting_rate(reversed_) == 0.0
+    # the worst-case total is 500 for ten realisations of ten series: one
+    # swapped neighbour pair in one realisation departs by 2
+    one_swap = [list(range(10)) for _ in range(10)]
+    one_swap[4][3], one_swap[4][4] = one_swap[4][4], one_swap[4][3]
+    assert oracle.sorting_rate(one_swap) == 100.0 * (500 - 2) / 500
+    # equal values keep the SNR order; NaN sorts after every number
+    assert oracle.sorting_rate([[0.5] * 10]) == 100.0
+    nan_first = [[float("nan")] + list(range(1, 10))]
+    # series 1 moves to position 10, series j (j >= 2) to j - 1: departure 9 + 9
+    assert oracle.sorting_rate(nan_first) == 100.0 * (50 - 18) / 50
+
+
+def test_grid_select_brute_force():
+    # RR at each grid threshold from the explicit key matrix of the rescaled
+    # series, then the closest grid RR per target by a plain scan
+    y = rng(21).standard_normal(70).astype(np.float32)
+    for m, tau, norm in ((1, 1, 0), (3, 3, 0), (2, 2, 1)):
+        y64 = y.astype(np.float64)
+        y01 = ((y64 - y64.min()) / (y64.max() - y64.min())).astype(np.float32)
+        K = np_key_matrix(y01, m, tau, norm)
+        nv = K.shape[0]
+        upper = K[np.triu_indices(nv, 1)]
+        n_grid = 50
+        grid = np.array([(i / n_grid) if norm == 0 else (i / n_grid) ** 2 for i in range(1, n_grid + 1)],
+                        dtype=np.float32)
+        rr = np.array([np.sum(upper <= g) for g in grid]) / upper.size
+        targets = [0.01, 0.1, 0.37, 0.9]
+        eps, got_rr, err = oracle.grid_select(y, m, tau, norm, 1, targets, n_grid=n_grid)
+        for t, e, r, d in zip(targets, eps, got_rr, err):
+            best = min(range(n_grid), key=lambda i: (abs(rr[i] - t), i))
+            assert e == grid[best] and r == rr[best] and d == abs(rr[best] - t)
