@@ -395,7 +395,7 @@ constexpr uint32_t P1_COPIES = RQA_P1_COPIES;
 __host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G)
 {
     if (pass == 1) return SEL_N1 * 4 * P1_COPIES;
-    if (pass == 2) return SEL_N1 * 2 + (size_t)G * SEL_N2 * 4;
+    if (pass == 2) return SEL_N1 * 2 + (size_t)G * SEL_N2 * 4 + TILE_W * 4;
     return SEL_N1 + (size_t)K * SEL_N2;
 }
 
@@ -437,7 +437,7 @@ constexpr uint16_t NO_BIN = 0xFFFF;
 template <int NORM, int MC, int TC>
 struct SelPass2 {
     uint16_t* sOff;   // LDS [SEL_N1]: first bin of the bucket's slot in this group, or NO_BIN
-    uint32_t* bins;   // LDS [G][SEL_N2]
+    uint32_t* bins;   // LDS [G][SEL_N2] + one spare word per lane
     const uint8_t* T1;
     const SeriesWork* works;
     uint64_t* h2;     // global [S][K][SEL_N2]
@@ -469,12 +469,16 @@ struct SelPass2 {
     {
         return sOff[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
     }
+    // keys outside this group's target buckets count into a spare word per
+    // lane, so the count needs no branch (and no divergence)
+    uint32_t dummy = 0;
     __device__ __forceinline__ void count(uint32_t u, uint32_t off) const
     {
-        if (off != NO_BIN) atomicAdd(&bins[off + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)], 1u);
+        atomicAdd(&bins[off != NO_BIN ? off + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2) : dummy], 1u);
     }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
+        dummy = G * SEL_N2 + (uint32_t)lane;
         select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
     }
 };
@@ -2195,6 +2199,8 @@ struct WinPass1 {
     {
         const uint32_t rel = u - lo;
         below += u < lo ? 1u : 0u;
+        // a branch: most keys lie outside the window, and an atomic per key
+        // would cost more than the divergence
         if (rel <= span) atomicAdd(&bins[rel >> shift], 1u);
     }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
