@@ -78,27 +78,41 @@ def test_medium_systems_full_length(ctx, idx):
     check_case(ctx, synth.config_medium()[idx])
 
 
-def test_large_lorenz_sampled(ctx):
-    """N=10^5, m=3, tau=5, Euclidean, K=20 (4,998,950,055 pairs).  The oracle
-    cannot sort 5e9 keys in a test, so two sampled targets are checked through
-    properties that pin them at any size: the order-statistic bracket
-    #{key < eps} < k <= #{key <= eps} = count, and the line statistics at that
-    threshold recomputed by the oracle's plain per-threshold run-length pass."""
-    case = synth.config_large(which="lorenz")[0]
-    print(f"[parity] {case['name']} full size", flush=True)
-    got = ctx.run(dev(case["y"]), prm(case), case["rr"])
-    M = oracle.num_pairs(oracle.num_vectors(len(case["y"]), 3, 5), 1)
+def test_large_bench_batch(ctx):
+    """The bench step: both N = 10^5 series (m = 3, tau = 5, Euclidean, K = 20,
+    4,998,950,055 pairs each) in one rqa_batch call.  The oracle cannot sort
+    5e9 keys in a test, so every threshold is pinned through properties that
+    hold at any size: the order-statistic bracket #{key < eps_r} < k_r <=
+    #{key <= eps_r} = count_r, and RR and DET at that threshold recomputed
+    by the oracle's plain per-threshold run-length pass, for all 20 targets
+    of both series."""
+    import torch
+    cases = synth.config_large()
+    prm_ = [prm(c) for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(c["y"]) for c in cases])]).astype(np.uint64)
+    concat = torch.from_numpy(np.concatenate([c["y"] for c in cases])).to("cuda:0")
+    rr = np.stack([c["rr"] for c in cases])
+    print("[parity] bench batch 2 x N=1e5", flush=True)
+    got = ctx.batch(concat, offs, prm_, rr)
+    M = oracle.num_pairs(oracle.num_vectors(100_000, 3, 5), 1)
     assert M == 4998950055
-    for r in (0, 19):
-        assert int(got["k"][r]) == oracle.rank(case["rr"][r], M)
-    sample = got["eps"][[0, 19]]
-    lt, le = oracle.count(case["y"], 3, 5, 1, 1, sample)
-    for i, r in enumerate((0, 19)):
-        assert lt[i] < got["k"][r] <= le[i]
-        assert le[i] == got["count"][r]
-    lin = oracle.lines(case["y"], 3, 5, 1, 1, 2, got["eps"][[19]])
-    assert lin["count"][0] == got["count"][19]
-    assert lin["det"][0] == got["det"][19]
+    for s, targets in ((0, list(range(20))), (1, list(range(20)))):
+        c = cases[s]
+        eps = got["eps"][s][targets]
+        print(f"[parity] {c['name']} oracle counts at {len(targets)} thresholds", flush=True)
+        lt, le = oracle.count(c["y"], 3, 5, 1, 1, eps)
+        for i, r in enumerate(targets):
+            k = oracle.rank(c["rr"][r], M)
+            assert lt[i] < k <= le[i]
+            assert le[i] == got["count"][s][r]
+        print(f"[parity] {c['name']} oracle lines at {len(targets)} thresholds", flush=True)
+        lin = oracle.lines(c["y"], 3, 5, 1, 1, 2, eps)
+        assert np.array_equal(lin["count"], got["count"][s][targets])
+        assert np.array_equal(lin["rr"], got["rr"][s][targets])
+        assert np.array_equal(lin["det"], got["det"][s][targets])
+    # the averaged DET is the left-to-right mean of the 20 DET values
+    for s in range(2):
+        assert got["det_mean"][s] == sum(got["det"][s].tolist()) / 20
 
 
 # ---------------------------------------------------------------- golden plots
