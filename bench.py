@@ -268,7 +268,19 @@ def bench_k99(ctx, torch, rqa, concat, offs, prm, nseries, cells, steps):
         got99 = ctx.batch(concat, offs, prm, rr99)
     torch.cuda.synchronize()
     sec99 = (time.perf_counter() - t0) / steps
+    ph99 = ctx.phase_times()
+    # the same with the sketch-sample window (identical results)
+    win = ctx.batch(concat, offs, prm, rr99, flags=rqa.RQA_SEL_SAMPLE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        win = ctx.batch(concat, offs, prm, rr99, flags=rqa.RQA_SEL_SAMPLE)
+    torch.cuda.synchronize()
+    secw = (time.perf_counter() - t0) / steps
     return {"ms_per_step": sec99 * 1e3, "value": cells * 99 / sec99, "unit": "cell-thresholds/s",
+            "phases_ms": ph99,
+            "sample_window_ms_per_step": secw * 1e3,
+            "sample_window_identical": bool(all(np.array_equal(win[k], got99[k]) for k in ("eps", "count", "det"))),
             "averaged_det_curve_end": [float(rqa.rqa_averaged_det(d)[-1]) for d in got99["det"]]}
 
 

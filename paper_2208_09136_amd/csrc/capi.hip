@@ -874,10 +874,27 @@ void finish_lines(Job& job)
 // counts C and D in the same pass.  With many targets its histograms do not
 // fit the LDS: then the thresholds are selected completely first and a sweep
 // at them follows.  stat_passes counts every full pass over the pairs.
+// The range sweep (counting passes, then ranks against the candidate ranges
+// left by them) while it is the faster path, else complete selection and the
+// threshold sweep.  The range sweep's cost grows with K (a per-lane
+// line-rank histogram of 2K + 1 rows in LDS, and more keys inside candidate
+// ranges take its fine-counter path), the threshold sweep's hardly does.
+// Measured crossovers on MI355X (two N = 1e5 series): between K = 40 and 60
+// with plain selection (14.1 / 14.5 ms at K = 40, 16.6 / 14.6 at 60, 30.2 /
+// 19.1 at 99), between K = 20 and 40 with a window (8.1 / 10.2 ms at K = 20,
+// 13.1 / 11.8 at 40), whose candidate ranges are eight times wider.
+constexpr uint32_t FUSED_MAX_K_PLAIN = 48;
+constexpr uint32_t FUSED_MAX_K_WINDOW = 30;
+
+bool use_fused(const rqa_ctx* c, uint32_t K, int sel)
+{
+    return K <= (sel == 0 ? FUSED_MAX_K_PLAIN : FUSED_MAX_K_WINDOW) && sweep_lds_bytes(2 * K + 1, true) <= c->max_lds;
+}
+
 rqa_status select_and_sweep(rqa_ctx* c, Job& job)
 {
     rqa_status st;
-    if (sweep_lds_bytes(2 * job.K + 1, true) <= c->max_lds) {
+    if (use_fused(c, job.K, job.sel)) {
         job.mode = MODE_FUSED;
         if (job.sel == 0) {
             c->stat_passes = 3;
@@ -990,7 +1007,7 @@ rqa_status tune_job(rqa_ctx* c, Job& job, uint32_t* seg_out, uint32_t* chunk_out
     rqa_status st = RQA_OK;
     uint32_t last_seg = 0;
     // tune the path the calls take (see select_and_sweep)
-    const int mode = (job.mode == MODE_FUSED && sweep_lds_bytes(2 * K + 1, true) > c->max_lds) ? MODE_BOTH : job.mode;
+    const int mode = (job.mode == MODE_FUSED && !use_fused(c, K, job.sel)) ? MODE_BOTH : job.mode;
     for (auto& kv : buckets) {
         Job sub;
         sub.base = job.base;

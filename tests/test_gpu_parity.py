@@ -387,3 +387,25 @@ def test_paper_rr_set_k99(ctx, system, m, tau, norm):
     assert curve[-1] == got["det_mean"]
     win = ctx.run(dev(y), prm(case), RR_99, flags=4)
     assert np.array_equal(win["eps"], got["eps"]) and np.array_equal(win["det"], got["det"])
+
+
+@pytest.mark.parametrize("K", [21, 30, 31, 48, 49, 64])
+def test_path_switch_by_k(ctx, K):
+    # the library switches between the range sweep and complete selection
+    # plus the threshold sweep by K and selection method; every side of each
+    # switch gives the oracle's thresholds, RR and DET
+    y = synth.series("lorenz", 2500, 5.0, (11, K, 0, 0))
+    rr = np.array([0.003 + 0.6 * k / K for k in range(K)])
+    case = {"name": f"switch_k{K}", "y": y, "m": 3, "tau": 5, "norm": 1, "theiler": 1, "lmin": 2, "rr": rr}
+    print(f"[parity] {case['name']}", flush=True)
+    got = check_case(ctx, case)
+    for flags in (4, 1):
+        if flags == 1:
+            from paper_2208_09136_amd import bracket
+            import os
+            path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                "paper_2208_09136_amd", "bracket_params.npz")
+            bracket.load(ctx, path)
+        win = ctx.run(dev(y), prm(case), rr, flags=flags)
+        for key in ("eps", "count", "rr", "det", "det_mean"):
+            assert np.array_equal(win[key], got[key]), (flags, key)
