@@ -160,12 +160,14 @@ __device__ __forceinline__ TileGeo tile_geo(const SeriesScalars& sd, uint32_t ti
 // least 8): each half-block writes HU new parts into one half while the last W
 // parts of the other half serve as history, so the ring never moves.  Row
 // samples y[s] are wave-uniform (scalar loads); column samples y[s + d] are
-// one coalesced load per step at an immediate offset from the lane pointer.
+// one coalesced load per step at an immediate offset from the lane pointer,
+// issued one half-block ahead.
 template <int NORM, int M, int TAU>
 struct Walker {
     static constexpr int W = (M - 1) * TAU;
     static constexpr int HU = W == 0 ? 8 : ((8 + W - 1) / W) * W;
     float ring[2 * HU];
+    float cnext[HU];  // column samples of the next half-block, loaded one half ahead
     const gf32* cp;  // y + d + x (this lane's column samples)
     const cf32* rp;  // y + x (row samples, uniform)
 
@@ -175,6 +177,8 @@ struct Walker {
         rp = (const cf32*)y + (uint32_t)x0;
 #pragma unroll
         for (int i = 0; i < W; ++i) ring[2 * HU - W + i] = part_of<NORM>(rp[i] - cp[i]);
+#pragma unroll
+        for (int u = 0; u < HU; ++u) cnext[u] = cp[W + u];
     }
     // part at virtual position v of the half-block that writes half H: v < W is
     // history (tail of the other half), v >= W the new part of step v - W.
@@ -187,8 +191,16 @@ struct Walker {
     template <int H>
     __device__ __forceinline__ void half(uint32_t (&out)[HU])
     {
+        float cv[HU];
 #pragma unroll
-        for (int u = 0; u < HU; ++u) ring[H * HU + u] = part_of<NORM>(rp[W + u] - cp[W + u]);
+        for (int u = 0; u < HU; ++u) cv[u] = cnext[u];
+        // the next half-block's column samples, so their latency overlaps this
+        // half-block's work: at most 2 HU - 1 cells past the requested range,
+        // inside the walker's slack
+#pragma unroll
+        for (int u = 0; u < HU; ++u) cnext[u] = cp[W + HU + u];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) ring[H * HU + u] = part_of<NORM>(rp[W + u] - cv[u]);
 #pragma unroll
         for (int u = 0; u < HU; ++u) {
             float acc = at<H>(u + W);  // component 0: the newest sample
@@ -214,7 +226,7 @@ __device__ __forceinline__ void walk(const float* y, int d, int x0, int count, F
 {
     using WK = Walker<NORM, M, TAU>;
     constexpr int HU = WK::HU;
-    static_assert(HU < WALK_SLACK, "walker slack");
+    static_assert(2 * HU - 1 <= WALK_SLACK, "walker slack (the last half-block prefetches one more)");
     WK wk;
     wk.start(y, d, x0);
     int rem = count;
