@@ -19,8 +19,11 @@ constexpr int TILE_W = 64;
 // last SEL_B3 bits of keys whose 21-bit prefix holds a target are resolved
 // either by pass 3 (selection only) or inside the line sweep (global
 // counters: few keys qualify).
-constexpr int SEL_B1 = 12;
-constexpr int SEL_B2 = 9;
+#ifndef RQA_SEL_B1
+#define RQA_SEL_B1 12
+#endif
+constexpr int SEL_B1 = RQA_SEL_B1;
+constexpr int SEL_B2 = 21 - SEL_B1;
 constexpr int SEL_B3 = 10;
 constexpr int SEL_SH1 = 31 - SEL_B1;           // 19
 constexpr int SEL_SH2 = SEL_SH1 - SEL_B2;      // 10
