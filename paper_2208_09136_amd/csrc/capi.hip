@@ -182,12 +182,12 @@ uint32_t segment_for(const rqa_ctx* c, uint64_t nv, const rqa_params& p, uint32_
 }
 
 // Segment of the histogram pass: the caller's override (at most
-// HIST_MAX_SEG_HOST), else about 48 segments on the longest diagonal
+// HIST_MAX_SEG_HOST), else about 96 segments on the longest diagonal
 // (256 .. 4096).
 uint32_t hist_segment_for(const rqa_ctx* c, uint64_t L0)
 {
     if (c->seg) return std::min<uint32_t>(c->seg, HIST_MAX_SEG_HOST);
-    const uint64_t t = (L0 + 47) / 48;
+    const uint64_t t = (L0 + 95) / 96;
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>((t + TILE_W - 1) / TILE_W * TILE_W, 256), 4096);
 }
 

@@ -1579,13 +1579,14 @@ struct HistBody {
     uint32_t tbase;       // this series' first tile in pre / suf
     bool multi;
     bool active = true;
-    // lane state: top (top_r, top_p) and next (nx_r, nx_p) of the stack; LDS rows
-    // [0, sp) hold the bottom sentinel and then the entries below next (sp >= 1);
+    // lane state: the top and next entries of the stack (packed); LDS rows
+    // [0, sp) hold the bottom sentinel and then the entries below next (sp >= 1),
+    // addressed by byte offsets: so = row sp of this lane, so0 / so1 = rows 0 / 1;
     // pm is the largest rank so far in the segment.  A cell of rank Kp ends every
     // run: it replaces the whole stack as a new bottom sentinel (rank Kp + 1 at
     // its position), so runs of such cells cost no pops.  Only the segment's own
     // sentinel has position t0.
-    uint32_t top_r, top_p, nx_r, nx_p, sp, pm, t0;
+    uint32_t top, nx, so, so0, so1, bd4, pm, t0;
     uint16_t* lpre;       // this lane's pre / suf column in the current tile
     uint16_t* lsuf;
 
@@ -1628,16 +1629,14 @@ struct HistBody {
             atomicAdd((unsigned long long*)&dser[(size_t)lb * kcap + b], ~0ull);
         }
     }
-    __device__ __forceinline__ uint32_t& row(uint32_t i) { return stk[(size_t)i * blockDim.x + threadIdx.x]; }
+    __device__ __forceinline__ uint32_t& at(uint32_t off) { return *(uint32_t*)((unsigned char*)stk + off); }
+    static constexpr uint32_t POS = 0xFFFFFFu;
     __device__ __forceinline__ void pop()
     {
-        top_r = nx_r;
-        top_p = nx_p;
+        top = nx;
         // row 0 is the bottom sentinel: below it is the sentinel again
-        const uint32_t e = row(sp - 1);
-        nx_r = e >> 24;
-        nx_p = e & 0xFFFFFFu;
-        sp = max(sp - 1, 1u);
+        nx = at(so - bd4);
+        so = max(so - bd4, so1);
     }
     // cell of rank r <= Kp at position t
     __device__ __forceinline__ void cell(uint32_t r, uint32_t t)
@@ -1648,21 +1647,22 @@ struct HistBody {
             for (uint32_t j = pm; j < r; ++j) lpre[(size_t)j * TILE_W] = (uint16_t)(t - t0);
             pm = r;
         }
-        while (top_r <= r) {
+        // pop while the top's rank is <= r (ranks sit in the high byte)
+        const uint32_t rhi = (r << 24) | POS;
+        while (top <= rhi) {
+            const uint32_t tr = top >> 24, np1 = nx & POS;
             // next is the segment's sentinel: a leading run, recorded above
-            const uint32_t b = nx_p == t0 ? top_r : min(nx_r, r);
-            if (top_r < b) line(t - nx_p, top_r, b);
+            const uint32_t b = np1 == t0 ? tr : min(nx >> 24, r);
+            if (tr < b) line(t - np1, tr, b);
             pop();
         }
         const bool reset = r == rc.Kp;
         const uint32_t snt = ((rc.Kp + 1) << 24) | (t + 1);
         // push: a cell below the top sends next to LDS (a sentinel next is row 0 already)
-        row(reset ? 0u : sp) = reset ? snt : (nx_r << 24) | nx_p;
-        sp = reset ? 1u : sp + (nx_r <= rc.Kp ? 1u : 0u);
-        nx_r = reset ? rc.Kp + 1 : top_r;
-        nx_p = reset ? t + 1 : top_p;
-        top_r = reset ? rc.Kp + 1 : r;
-        top_p = t + 1;
+        at(reset ? so0 : so) = reset ? snt : nx;
+        so = reset ? so1 : so + (nx < ((rc.Kp + 1) << 24) ? bd4 : 0u);
+        nx = reset ? snt : top;
+        top = reset ? snt : (r << 24) | (t + 1);
     }
     __device__ __forceinline__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
@@ -1679,10 +1679,12 @@ struct HistBody {
         lsuf = suf + col;
         t0 = (uint32_t)g.t0;
         // sentinel (rank Kp + 1 at position t0 - 1) as top, next and LDS row 0
-        top_r = nx_r = Kp + 1;
-        top_p = nx_p = t0;
-        row(0) = ((Kp + 1) << 24) | t0;
-        sp = 1;
+        bd4 = blockDim.x * 4u;
+        so0 = threadIdx.x * 4u;
+        so1 = so0 + bd4;
+        so = so1;
+        top = nx = ((Kp + 1) << 24) | t0;
+        at(so0) = top;
         pm = 0;
         constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
         bool done = false;
@@ -1717,19 +1719,19 @@ struct HistBody {
         // trailing runs: below the last cell's rank empty, then one per stack entry
         const uint32_t e = (uint32_t)g.t1;
         #pragma unroll 1
-        for (uint32_t j = 0; j < min(top_r, Kp); ++j) lsuf[(size_t)j * TILE_W] = 0;
-        while (top_r <= Kp) {
-            const uint32_t hi = min(nx_r, Kp);
-            if (nx_p == t0) {
-                // every cell of the segment recurrent at [top_r, Kp)
+        for (uint32_t j = 0; j < min(top >> 24, Kp); ++j) lsuf[(size_t)j * TILE_W] = 0;
+        while ((top >> 24) <= Kp) {
+            const uint32_t tr = top >> 24, hi = min(nx >> 24, Kp), np1 = nx & POS;
+            if (np1 == t0) {
+                // every cell of the segment recurrent at [tr, Kp)
                 #pragma unroll 1
-                for (uint32_t j = top_r; j < hi; ++j) {
+                for (uint32_t j = tr; j < hi; ++j) {
                     lpre[(size_t)j * TILE_W] = (uint16_t)(e - t0);
                     lsuf[(size_t)j * TILE_W] = (uint16_t)(e - t0);
                 }
             } else {
                 #pragma unroll 1
-                for (uint32_t j = top_r; j < hi; ++j) lsuf[(size_t)j * TILE_W] = (uint16_t)(e - nx_p);
+                for (uint32_t j = tr; j < hi; ++j) lsuf[(size_t)j * TILE_W] = (uint16_t)(e - np1);
             }
             pop();
         }
