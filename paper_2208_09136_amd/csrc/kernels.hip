@@ -2440,7 +2440,7 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t s)
 // SplitMix64, pair index v mod M in diagonal-major order), their keys sorted
 // in LDS, the median as scale, and the histogram of (bits - scale) >> 21
 // clamped to SKETCH_BINS quarter-binade bins.
-__global__ void __launch_bounds__(256) k_sketch(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+__global__ void __launch_bounds__(1024) k_sketch(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
                                                 float* __restrict__ features, uint32_t* __restrict__ sample_sorted)
 {
     __shared__ uint32_t keys[SKETCH_P];
@@ -2501,7 +2501,8 @@ __global__ void __launch_bounds__(256) k_sketch(const SeriesDesc* __restrict__ s
 
 hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint32_t* sample_sorted)
 {
-    hipLaunchKernelGGL(k_sketch, dim3(b.S), dim3(256), 0, st, b.sd, b.work, features, sample_sorted);
+    // 1024 threads: four sample keys per thread through the 78 bitonic stages
+    hipLaunchKernelGGL(k_sketch, dim3(b.S), dim3(1024), 0, st, b.sd, b.work, features, sample_sorted);
     return hipGetLastError();
 }
 
