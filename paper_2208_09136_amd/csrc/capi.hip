@@ -181,6 +181,11 @@ uint32_t segment_for(const rqa_ctx* c, uint64_t nv, const rqa_params& p, uint32_
     return default_segment(nv - p.theiler);
 }
 
+// The threshold sweep runs 1024-thread workgroups when its LDS (rank table,
+// per-lane histograms of K + 1 rows) admits only one workgroup per CU: at
+// K = 99 on two N = 1e5 series 6.1 -> 4.5 ms.
+bool wide_sweep(const rqa_ctx* c, uint32_t K) { return sweep_lds_bytes(K, false) * 2 > c->max_lds; }
+
 // Segment of the histogram pass: the caller's override (at most
 // HIST_MAX_SEG_HOST), else about 96 segments on the longest diagonal
 // (256 .. 4096).
@@ -319,6 +324,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     {
         const Series& z0 = job.series[0];
         CT = hist ? hist_block / TILE_W : chunk_for(c, S, z0.n - (uint64_t)(z0.p.m - 1) * z0.p.tau, z0.p, K);
+        // the wide threshold sweep needs a tile per wave of its 1024-thread workgroups
+        if ((job.mode & MODE_SWEEP) && !((job.mode & MODE_SELECT) && (job.mode & MODE_LINES)) && wide_sweep(c, K))
+            CT = std::max<uint32_t>(CT, 1024 / TILE_W);
     }
 
     // descriptors, ordered by kernel variant so each launch sees a contiguous range
@@ -630,7 +638,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         HIP_TRY(tm.begin(PH_SWEEP));
         for (const Group& g : groups) {
             DevBufs v = view(g);
-            const uint32_t block = 512;
+            const uint32_t block = (!fused && wide_sweep(c, K)) ? 1024 : 512;
             const size_t lds = sweep_lds_bytes(fused ? 2 * K + 1 : K, fused);
             const int per_cu = sweep_blocks_per_cu(g.swp, fused, block, lds);
             const uint32_t grid = c->grid ? c->grid

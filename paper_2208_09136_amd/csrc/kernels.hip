@@ -1319,8 +1319,10 @@ __host__ __device__ __forceinline__ size_t sweep_lds_bytes_dev(uint32_t rows, bo
     return RHO_TABLE * sizeof(uint2) + RANK_MAX * 4 + 2 * (size_t)(rows + 1) * TILE_W * 4;
 }
 
+// Launched with 512 threads, or 1024 where its LDS admits one workgroup per
+// CU (large K), so that more waves share the one copy of the tables.
 template <int NORM, int MC, int TC, int LMC>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_t chunk_tiles,
         uint32_t* __restrict__ ticket, SeriesWork* __restrict__ works, const uint2* __restrict__ rtab, uint32_t Kcap)
 {
