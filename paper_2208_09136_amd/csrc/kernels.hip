@@ -806,21 +806,10 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
     uint8_t* t2 = T2 + (size_t)s * K * SEL_N2;
     const uint32_t n2 = w.nslots2;
     const uint64_t* h2 = h2all + (size_t)s * K * SEL_N2;
+    (void)h2;
     for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) t2[i] = NO_SLOT;
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
-        const uint64_t* h = h2 + (size_t)w.slot[r] * SEL_N2;
-        const uint64_t want = w.k[r] - w.below[r];
-        uint64_t run = 0;
-        uint32_t c = 0;
-        for (; c < SEL_N2; ++c) {
-            if (run + h[c] >= want) break;
-            run += h[c];
-        }
-        if (c == SEL_N2) { c = SEL_N2 - 1; atomicOr(&w.status, 2u); }
-        w.below[r] += run;
-        w.prefix[r] = (w.prefix[r] << SEL_B2) | c;
-        uniq[r] = w.prefix[r];
-    }
+    // below / prefix of every target come from k_scan2_find
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) uniq[r] = w.prefix[r];
     __syncthreads();
     if (threadIdx.x == 0) nuniq = sort_unique(uniq, K);
     __syncthreads();
@@ -834,33 +823,71 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
     if (threadIdx.x == 0) w.nslots3 = nu;
 }
 
+// First bin of a target's histogram row whose prefix reaches want: one
+// workgroup (series, target); *c and *run (the sum below the bin) land in
+// LDS for thread 0.  A row that does not reach want (inconsistent counts)
+// gives its last bin, the row's total and status |= flag.
+__device__ void target_bin(const uint64_t* __restrict__ h, uint32_t n, uint64_t want, SeriesWork& w, uint32_t flag,
+                           uint64_t* pre, uint32_t* c, uint64_t* run)
+{
+    chunk_prefix(h, n, pre);
+    if (threadIdx.x == 0) {
+        if (pre[blockDim.x] >= want) {
+            *c = first_in_chunks(h, n, pre, want, run);
+        } else {
+            *c = n - 1;
+            *run = pre[blockDim.x];
+            atomicOr(&w.status, flag);
+        }
+    }
+}
+
+// Pass-2 bins of every target (workgroup per series and target), before k_scan2.
+__global__ void __launch_bounds__(256) k_scan2_find(const SeriesDesc* __restrict__ sds,
+                                                    SeriesWork* __restrict__ works, const uint64_t* __restrict__ h2all)
+{
+    __shared__ uint64_t pre[257];
+    __shared__ uint32_t s_c;
+    __shared__ uint64_t s_run;
+    const uint32_t s = blockIdx.x, r = blockIdx.y;
+    const uint32_t K = sds[s].K;
+    if (r >= K) return;
+    SeriesWork& w = works[s];
+    const uint64_t* h = h2all + (size_t)s * K * SEL_N2 + (size_t)w.slot[r] * SEL_N2;
+    target_bin(h, SEL_N2, w.k[r] - w.below[r], w, 2u, pre, &s_c, &s_run);
+    if (threadIdx.x == 0) {
+        w.below[r] += s_run;
+        w.prefix[r] = (w.prefix[r] << SEL_B2) | s_c;
+    }
+}
+
 // After pass 3: the last SEL_B3 bits give the threshold; count = #{key <= eps}.
+// Workgroup per series and target.
 __global__ void __launch_bounds__(256) k_scan3(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
                                                const uint64_t* __restrict__ h3)
 {
-    const uint32_t s = blockIdx.x;
+    __shared__ uint64_t pre[257];
+    __shared__ uint32_t s_c;
+    __shared__ uint64_t s_run;
+    const uint32_t s = blockIdx.x, r = blockIdx.y;
     const uint32_t K = sds[s].K;
+    if (r >= K) return;
     SeriesWork& w = works[s];
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
-        const uint64_t* h = h3 + ((size_t)s * K + w.slot[r]) * SEL_N3;
-        const uint64_t want = w.k[r] - w.below[r];
-        uint64_t run = 0;
-        uint32_t c = 0;
-        for (; c < SEL_N3; ++c) {
-            if (run + h[c] >= want) break;
-            run += h[c];
-        }
-        if (c == SEL_N3) { c = SEL_N3 - 1; atomicOr(&w.status, 4u); }
-        w.eps_bits[r] = (w.prefix[r] << SEL_B3) | c;
-        w.count[r] = w.below[r] + run + h[c];
+    const uint64_t* h = h3 + ((size_t)s * K + w.slot[r]) * SEL_N3;
+    target_bin(h, SEL_N3, w.k[r] - w.below[r], w, 4u, pre, &s_c, &s_run);
+    if (threadIdx.x == 0) {
+        w.eps_bits[r] = (w.prefix[r] << SEL_B3) | s_c;
+        w.count[r] = w.below[r] + s_run + h[s_c];
     }
 }
 
 hipError_t launch_select_scan(hipStream_t st, const DevBufs& b, int pass)
 {
     if (pass == 1) hipLaunchKernelGGL(k_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T1, b.h1);
-    else if (pass == 2) hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2);
-    else hipLaunchKernelGGL(k_scan3, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.h3);
+    else if (pass == 2) {
+        hipLaunchKernelGGL(k_scan2_find, dim3(b.S, b.K), dim3(256), 0, st, b.sd, b.work, b.h2);
+        hipLaunchKernelGGL(k_scan2, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.T2, b.h2);
+    } else hipLaunchKernelGGL(k_scan3, dim3(b.S, b.K), dim3(256), 0, st, b.sd, b.work, b.h3);
     return hipGetLastError();
 }
 
