@@ -299,7 +299,7 @@ struct Job {
     std::vector<uint8_t> hit;        // S*K, window selection: target resolved in the window
     uint32_t hist_len = 0;           // histogram mode: entries per row (length 0 .. hist_len-1)
     uint32_t hist_kp = 0;            // histogram mode: largest number of distinct thresholds
-    std::vector<uint64_t> hist;      // S*K*hist_len, P_r(l), caller order
+    uint64_t* hist_dst = nullptr;    // histogram mode: host rows S*K*hist_len, P_r(l), caller order
 };
 
 rqa_status ensure_acts(rqa_ctx* c, uint32_t B, MlpActs& a);
@@ -422,6 +422,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
     const size_t hist_words = hist ? (size_t)S * job.hist_len * (job.hist_kp + 1) : 0;
     const size_t o_dh = hist ? carve(sizeof(uint64_t) * hist_words) : 0;
+    const size_t o_hout = hist ? carve(sizeof(uint64_t) * (size_t)S * K * job.hist_len) : 0;
     // histogram: leading / trailing runs per tile, threshold and lane (written before read)
     std::vector<size_t> g_tile(groups.size(), 0);
     size_t hist_tiles = 0;
@@ -628,6 +629,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             const uint32_t jgrid = std::min<uint32_t>(items, (uint32_t)c->num_cu * 4);
             HIP_TRY(launch_hist_join(sm, v, jgrid, pre, suf, dg, job.hist_len, job.hist_kp));
         }
+        HIP_TRY(launch_hist_finish(sm, all, (const uint64_t*)(pool + o_dh), (uint64_t*)(pool + o_hout), job.hist_len,
+                                   job.hist_kp));
         HIP_TRY(tm.end());
     }
     if ((job.mode & MODE_SWEEP) || fused) {
@@ -656,29 +659,16 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     }
     HIP_TRY(hipMemcpyAsync(h_out, all.work, hs_work, hipMemcpyDeviceToHost, sm));
     if (hs_feat) HIP_TRY(hipMemcpyAsync(h_feat, pool + o_feat, hs_feat, hipMemcpyDeviceToHost, sm));
-    std::vector<uint64_t> h_dh(hist_words);
-    if (hist) HIP_TRY(hipMemcpyAsync(h_dh.data(), pool + o_dh, sizeof(uint64_t) * hist_words, hipMemcpyDeviceToHost, sm));
+    if (hist) {
+        // rows straight into the caller's buffer, series back in caller order
+        if (!job.hist_dst) return fail(RQA_ERR_INVALID_ARG, "histogram destination is NULL");
+        const size_t rows = (size_t)K * job.hist_len;
+        for (uint32_t i = 0; i < S; ++i)
+            HIP_TRY(hipMemcpyAsync(job.hist_dst + (size_t)order[i] * rows, (uint64_t*)(pool + o_hout) + (size_t)i * rows,
+                                   sizeof(uint64_t) * rows, hipMemcpyDeviceToHost, sm));
+    }
     HIP_TRY(hipStreamSynchronize(sm));
     tm.collect();
-    if (hist) {
-        // P_j(l) = prefix over thresholds of the difference counts; rows in caller order
-        const uint32_t kc = job.hist_kp + 1, L = job.hist_len;
-        job.hist.assign((size_t)S * K * L, 0);
-        std::vector<int64_t> run(kc);
-        for (uint32_t i = 0; i < S; ++i) {
-            const uint32_t s = order[i];
-            const SeriesWork& w = h_out[i];
-            for (uint32_t l = 0; l < L; ++l) {
-                const uint64_t* d = &h_dh[((size_t)i * L + l) * kc];
-                int64_t acc = 0;
-                for (uint32_t j = 0; j < kc; ++j) {
-                    acc += (int64_t)d[j];
-                    run[j] = acc;
-                }
-                for (uint32_t r = 0; r < K; ++r) job.hist[((size_t)s * K + r) * L + l] = (uint64_t)run[w.dmap[r]];
-            }
-        }
-    }
 
     // results, back in caller order
     job.eps.assign((size_t)S * K, 0.f);
@@ -1230,8 +1220,8 @@ rqa_status rqa_det_curve(rqa_ctx* c, const float* series, uint64_t n, const rqa_
         hj.eps_bits = job.eps_bits;
         hj.hist_len = (uint32_t)hist_len;
         hj.hist_kp = kp;
+        hj.hist_dst = hist_out;
         if ((st = run_job(c, hj))) return st;
-        std::memcpy(hist_out, hj.hist.data(), sizeof(uint64_t) * (size_t)K * hist_len);
     }
     for (uint32_t r = 0; r < K; ++r) {
         count_out[r] = job.count[r];

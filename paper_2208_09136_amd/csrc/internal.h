@@ -181,6 +181,9 @@ hipError_t launch_hist(hipStream_t st, const DevBufs& b, int select_variant, uin
                        uint64_t* dglob, uint16_t* pre, uint16_t* suf, uint32_t hist_len, uint32_t Kp, uint32_t ticket);
 hipError_t launch_hist_join(hipStream_t st, const DevBufs& b, uint32_t grid, const uint16_t* pre,
                             const uint16_t* suf, uint64_t* dglob, uint32_t hist_len, uint32_t Kp);
+// P_r(l) rows out[S][K][hist_len] (caller threshold order) from dglob.
+hipError_t launch_hist_finish(hipStream_t st, const DevBufs& b, const uint64_t* dglob, uint64_t* out,
+                              uint32_t hist_len, uint32_t Kp);
 size_t hist_lds_bytes(uint32_t Kp, uint32_t block);
 int hist_blocks_per_cu(int select_variant, uint32_t Kp, uint32_t block);
 constexpr uint32_t HIST_MAX_K_HOST = RQA_MAX_HIST_K;

@@ -1862,6 +1862,35 @@ k_hist_join(const SeriesDesc* __restrict__ sds, const SeriesWork* __restrict__ w
     }
 }
 
+// P_r(l) from the difference counts: the prefix over thresholds up to the
+// caller's threshold r (dmap), written as rows out[s][r][l] (thread per l).
+__global__ void __launch_bounds__(256)
+k_hist_finish(const SeriesDesc* __restrict__ sds, const SeriesWork* __restrict__ works,
+              const uint64_t* __restrict__ dglob, uint64_t* __restrict__ out, uint32_t hist_len, uint32_t kcap)
+{
+    const uint32_t s = blockIdx.y;
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= hist_len) return;
+    const uint32_t K = sds[s].K;
+    const SeriesWork& w = works[s];
+    const uint64_t* d = dglob + ((size_t)s * hist_len + l) * kcap;
+    uint64_t* o = out + (size_t)s * K * hist_len + l;
+    for (uint32_t r = 0; r < K; ++r) {
+        const uint32_t top = min(w.dmap[r], kcap - 1);
+        uint64_t acc = 0;  // two's complement: the sum of the signed differences
+        for (uint32_t j = 0; j <= top; ++j) acc += d[j];
+        o[(size_t)r * hist_len] = acc;
+    }
+}
+
+hipError_t launch_hist_finish(hipStream_t st, const DevBufs& b, const uint64_t* dglob, uint64_t* out,
+                              uint32_t hist_len, uint32_t Kp)
+{
+    hipLaunchKernelGGL(k_hist_finish, dim3((hist_len + 255) / 256, b.S), dim3(256), 0, st, b.sd, b.work, dglob, out,
+                       hist_len, Kp + 1);
+    return hipGetLastError();
+}
+
 size_t hist_lds_bytes(uint32_t Kp, uint32_t block) { return hist_lds_bytes_dev(Kp, block) + 16; }
 
 using HistFn = void (*)(const SeriesDesc*, uint32_t, uint32_t, uint32_t, uint32_t*, SeriesWork*, const uint2*,
