@@ -422,7 +422,6 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_wbins = window ? carve(sizeof(uint64_t) * S * WIN_BINS) : 0;
     const size_t hist_words = hist ? (size_t)S * job.hist_len * (job.hist_kp + 1) : 0;
     const size_t o_dh = hist ? carve(sizeof(uint64_t) * hist_words) : 0;
-    const size_t o_hout = hist ? carve(sizeof(uint64_t) * (size_t)S * K * job.hist_len) : 0;
     // histogram: leading / trailing runs per tile, threshold and lane (written before read)
     std::vector<size_t> g_tile(groups.size(), 0);
     size_t hist_tiles = 0;
@@ -434,6 +433,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_pre = hist ? carve(sizeof(uint16_t) * run_words) : 0;
     const size_t o_suf = hist ? carve(sizeof(uint16_t) * run_words) : 0;
     const size_t zero_end = off;  // tickets and histograms are cleared every call
+    // histogram rows: every entry written by the finishing kernel
+    const size_t o_hout = hist ? carve(sizeof(uint64_t) * (size_t)S * K * job.hist_len) : 0;
     const size_t o_T1 = carve((size_t)S * SEL_N1);
     const size_t o_T2 = carve((size_t)S * K * SEL_N2);
     const size_t o_rt = carve(sizeof(uint2) * S * RHO_TABLE);
