@@ -88,7 +88,7 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              f"`python -c 'import __graft_entry__ as g; g.build()'`")
+                              f"`python -m paper_2208_09136_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
