@@ -933,15 +933,22 @@ struct RangeCtx {
     const uint4* table;     // LDS [RANGE_TABLE]
     const uint32_t* es;     // LDS [Kp] boundaries
     float emin, emax;
-    uint32_t shift, Kp, z;
+    uint32_t sh4, Kp, z;    // sh4 = bucket shift - 4 (the shift is at least 4)
 };
 
+// Written with the operations gfx950 issues at the double rate (32-bit add,
+// sub, and, or, right shifts): the bucket's byte offset is a right shift and
+// a mask instead of a bit-field extract and a scaled add, and the two
+// compares are sign bits of differences instead of compare-and-select pairs.
+// Keys are at most +inf (0x7F800000) and boundaries at most 0x7FFFFFFF (the
+// absent-boundary value), so b - u cannot wrap and its sign bit is u > b.
 template <bool MULTI>
 __device__ __forceinline__ uint32_t rank_of(uint32_t u, const RangeCtx& c)
 {
     const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
-    const uint4 e = c.table[__builtin_amdgcn_ubfe(cl, c.shift, RANGE_BITS)];
-    uint32_t r = e.z + (u > e.x ? 1u : 0u) + (u > e.y ? 1u : 0u);
+    const uint32_t off = (cl >> c.sh4) & ((RANGE_TABLE - 1u) << 4);
+    const uint4 e = *(const uint4*)((const unsigned char*)c.table + off);
+    uint32_t r = e.z + ((e.x - u) >> 31) + ((e.y - u) >> 31);
     if constexpr (MULTI) {
         if (e.w) {
             r = e.z;
@@ -1152,7 +1159,7 @@ struct RangeBody {
         rc.es = ses;
         rc.emin = __uint_as_float(uniform(w.emin));
         rc.emax = __uint_as_float(uniform(w.emax));
-        rc.shift = uniform(w.shift);
+        rc.sh4 = uniform(w.shift) - 4u;
         rc.Kp = uniform(w.Kp);
         rc.z = uniform(w.zbase);
         spare = rc.Kp + rc.z;
@@ -1233,17 +1240,21 @@ struct RangeBody {
                     uint32_t rm1 = rank_at<MULTI>(km1), r0 = rank_at<MULTI>(k0);
                     walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                         uint32_t r[HU];
+                        // a line value is one of the ranks of its cell and the two
+                        // neighbours, so an odd rank among those of the block and the
+                        // two before it covers every odd key rank and line rank
+                        uint32_t acc = rm1 | r0;
 #pragma unroll
-                        for (int u = 0; u < HU; ++u) r[u] = rank_of<MULTI>(k[u], c);
-                        uint32_t acc = 0;
+                        for (int u = 0; u < HU; ++u) {
+                            r[u] = rank_of<MULTI>(k[u], c);
+                            acc |= r[u];
+                        }
 #pragma unroll
                         for (int u = 0; u < HU; ++u) {
                             if (u < valid) {
                                 const uint32_t cr = u == 0 ? r0 : r[u - 1];
                                 const uint32_t left = u == 0 ? rm1 : (u == 1 ? r0 : r[u - 2]);
-                                const uint32_t lam = max(cr, min(left, r[u]));
-                                emit(lam, lane);
-                                acc |= cr | lam;
+                                emit(max(cr, min(left, r[u])), lane);
                             }
                         }
                         if (__ballot(acc & 1u)) {
@@ -1940,15 +1951,16 @@ int hist_blocks_per_cu(int select_variant, uint32_t Kp, uint32_t block)
 
 
 // Range table of one series over the ascending boundaries es[0..kp) with rank
-// base z: RANGE_TABLE buckets of 2^shift bit patterns from es[0] to
-// es[kp-1]; each holds the first two boundaries inside it (x, y; ~0 when
-// absent), z + the boundaries below it, and w = the count when more than two
-// lie inside (compared one by one).  Called by a whole block.
+// base z: RANGE_TABLE buckets of 2^shift bit patterns (shift >= 4) from es[0]
+// to es[kp-1]; each holds the first two boundaries inside it (x, y;
+// 0x7FFFFFFF, above every key, when absent), z + the boundaries below it, and
+// w = the count when more than two lie inside (compared one by one).  Called
+// by a whole block.
 __device__ void build_range_table(SeriesWork& w, const uint32_t* es, uint32_t kp, uint32_t z, uint4* tab,
                                   uint32_t* s_shift)
 {
     if (threadIdx.x == 0) {
-        uint32_t sh = 0;
+        uint32_t sh = 4;
         while (sh < 31 && (es[kp - 1] >> sh) - (es[0] >> sh) >= RANGE_TABLE) ++sh;
         *s_shift = sh;
         w.multi = 0u;  // set before the barrier; table entries below may raise it
@@ -1968,7 +1980,7 @@ __device__ void build_range_table(SeriesWork& w, const uint32_t* es, uint32_t kp
     const uint32_t a0 = emin >> sh, a1 = emax >> sh;
     for (uint32_t idx = threadIdx.x; idx < RANGE_TABLE; idx += blockDim.x) {
         const uint32_t a = a0 + ((idx - a0) & (RANGE_TABLE - 1));
-        uint4 e = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, z, 0u);
+        uint4 e = make_uint4(0x7FFFFFFFu, 0x7FFFFFFFu, z, 0u);
         if (a <= a1) {
             const uint64_t lo = (uint64_t)a << sh, hi = (uint64_t)(a + 1) << sh;
             uint32_t below = 0, inside = 0;
@@ -1976,8 +1988,8 @@ __device__ void build_range_table(SeriesWork& w, const uint32_t* es, uint32_t kp
                 below += (uint64_t)es[i] < lo;
                 inside += ((uint64_t)es[i] >= lo) && ((uint64_t)es[i] < hi);
             }
-            e.x = inside >= 1 ? es[below] : 0xFFFFFFFFu;
-            e.y = inside >= 2 ? es[below + 1] : 0xFFFFFFFFu;
+            e.x = inside >= 1 ? es[below] : 0x7FFFFFFFu;
+            e.y = inside >= 2 ? es[below + 1] : 0x7FFFFFFFu;
             e.z = z + below;
             e.w = inside >= 3 ? inside : 0u;
             if (inside >= 3) w.multi = 1u;
