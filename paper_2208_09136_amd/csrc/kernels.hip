@@ -403,12 +403,15 @@ __device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t ti
 // P1_COPIES, so lanes of one wave that hit the same bucket hit different words.
 constexpr uint32_t P1_COPIES = RQA_P1_COPIES;
 
+// Sets of the pass-3 prefix table (two entries each).
+constexpr uint32_t P3_SETS = 4096;
+
 // Bytes of a selection pass's LDS tables and bins; the work-queue word follows.
 __host__ __device__ __forceinline__ size_t select_lds_bytes_dev(int pass, uint32_t K, uint32_t G)
 {
     if (pass == 1) return SEL_N1 * 4 * P1_COPIES;
     if (pass == 2) return SEL_N1 * 2 + (size_t)G * SEL_N2 * 4 + TILE_W * 4;
-    return SEL_N1 + (size_t)K * SEL_N2;
+    return P3_SETS * 8 + RQA_MAX_K * 2 + 16;
 }
 
 // Pass 1: histogram of the top SEL_B1 bits of every key.
@@ -497,39 +500,91 @@ struct SelPass2 {
 
 // Pass 3 (selection only): for keys whose 21-bit prefix holds a target,
 // count the last SEL_B3 bits per pass-3 slot directly in global memory (few
-// keys qualify).
+// keys qualify).  The target prefixes sit in an LDS table of P3_SETS sets of
+// two entries (prefix << 7 | pass-3 slot), indexed by the prefix's low bits,
+// so a key takes one 8-byte table read.  A series with three target prefixes
+// in one set (rare) looks its keys up in the pass-1 and pass-2 slot tables in
+// global memory instead, two dependent reads.
+constexpr uint32_t P3_EMPTY = 0xFFFFFFFFu;  // prefix field above every 21-bit prefix
+constexpr uint32_t P3_NONE = 0xFFFFFFFFu;   // key outside every target prefix
+static_assert(RQA_MAX_K <= 128, "pass-3 slots take 7 bits of a prefix-table entry");
+
 template <int NORM, int MC, int TC>
 struct SelPass3 {
-    uint8_t* sT1;     // LDS [SEL_N1]
-    uint8_t* sT2;     // LDS [K][SEL_N2]
+    uint2* sH;        // LDS [P3_SETS]: two entries prefix << 7 | pass-3 slot
+    uint16_t* sB;     // LDS [RQA_MAX_K]: pass-1 bucket of each pass-2 slot
+    uint32_t* sOver;  // LDS word: some set overflowed
     const uint8_t* T1;
     const uint8_t* T2;
     const SeriesWork* works;
     uint64_t* h3;     // global [S][K][SEL_N3]
     uint32_t K;
     unsigned long long* dst;
+    const uint8_t* gT1;  // this series' slot tables (overflow lookups)
+    const uint8_t* gT2;
+    bool over = false;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
         const uint32_t n2 = works[s].nslots2;
-        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) sT1[i] = T1[(size_t)s * SEL_N1 + i];
-        for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) sT2[i] = T2[(size_t)s * K * SEL_N2 + i];
+        gT1 = T1 + (size_t)s * SEL_N1;
+        gT2 = T2 + (size_t)s * K * SEL_N2;
+        for (uint32_t i = threadIdx.x; i < P3_SETS; i += blockDim.x) sH[i] = make_uint2(P3_EMPTY, P3_EMPTY);
+        for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) {
+            const uint32_t t = gT1[i];
+            if (t != NO_SLOT) sB[t] = (uint16_t)i;
+        }
+        if (threadIdx.x == 0) *sOver = 0u;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) {
+            const uint32_t s3 = gT2[i];
+            if (s3 == NO_SLOT) continue;
+            const uint32_t pfx = ((uint32_t)sB[i / SEL_N2] << SEL_B2) | (i % SEL_N2);
+            const uint32_t ent = (pfx << 7) | s3;
+            uint2& e = sH[pfx & (P3_SETS - 1)];
+            if (atomicCAS(&e.x, P3_EMPTY, ent) != P3_EMPTY && atomicCAS(&e.y, P3_EMPTY, ent) != P3_EMPTY)
+                *sOver = 1u;
+        }
+        __syncthreads();
+        over = uniform(*sOver) != 0u;
         dst = (unsigned long long*)(h3 + (size_t)s * K * SEL_N3);
     }
     __device__ void flush(uint32_t) {}
-    // pass-3 slot of the key's 21-bit prefix (NO_SLOT: none)
-    __device__ __forceinline__ uint32_t look(uint32_t u) const
-    {
-        const uint32_t s2 = sT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
-        return s2 != NO_SLOT ? (uint32_t)sT2[s2 * SEL_N2 + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)] : NO_SLOT;
-    }
-    __device__ __forceinline__ void count(uint32_t u, uint32_t s3) const
-    {
-        wave_add(dst, s3 * SEL_N3 + (u & (SEL_N3 - 1)), s3 != NO_SLOT);
-    }
+    // counter index of the key (P3_NONE: outside every target prefix): one
+    // table read at a byte offset made by a right shift and a mask
+    struct Table {
+        const SelPass3& b;
+        __device__ __forceinline__ uint32_t look(uint32_t u) const
+        {
+            const uint32_t off = (u >> (SEL_SH2 - 3)) & ((P3_SETS - 1u) << 3);
+            const uint2 e = *(const uint2*)((const unsigned char*)b.sH + off);
+            const uint32_t pfx = u >> SEL_SH2, lo = u & (SEL_N3 - 1);
+            const bool hx = (e.x >> 7) == pfx, hy = (e.y >> 7) == pfx;
+            const uint32_t ent = hx ? e.x : e.y;
+            return (hx || hy) ? ((ent & 127u) << SEL_B3) | lo : P3_NONE;
+        }
+        __device__ __forceinline__ void count(uint32_t, uint32_t idx) const { wave_add(b.dst, idx, idx != P3_NONE); }
+    };
+    struct Slots {
+        const SelPass3& b;
+        __device__ __forceinline__ uint32_t look(uint32_t u) const
+        {
+            const uint32_t s2 = b.gT1[__builtin_amdgcn_ubfe(u, SEL_SH1, SEL_B1)];
+            if (s2 == NO_SLOT) return P3_NONE;
+            const uint32_t s3 = b.gT2[s2 * SEL_N2 + __builtin_amdgcn_ubfe(u, SEL_SH2, SEL_B2)];
+            return s3 != NO_SLOT ? s3 * SEL_N3 + (u & (SEL_N3 - 1)) : P3_NONE;
+        }
+        __device__ __forceinline__ void count(uint32_t, uint32_t idx) const { wave_add(b.dst, idx, idx != P3_NONE); }
+    };
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
-        select_tile<NORM, MC, TC>(sd, tile_id, lane, *this);
+        if (over) {
+            Slots v{*this};
+            select_tile<NORM, MC, TC>(sd, tile_id, lane, v);
+        } else {
+            Table v{*this};
+            select_tile<NORM, MC, TC>(sd, tile_id, lane, v);
+        }
     }
 };
 
@@ -559,8 +614,9 @@ k_select(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint3
         chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, slot);
     } else {
         SelPass3<NORM, MC, TC> body;
-        body.sT1 = (uint8_t*)smem;
-        body.sT2 = (uint8_t*)(smem + SEL_N1);
+        body.sH = (uint2*)smem;
+        body.sB = (uint16_t*)(smem + P3_SETS * 8);
+        body.sOver = (uint32_t*)(smem + P3_SETS * 8 + RQA_MAX_K * 2);
         body.T1 = T1;
         body.T2 = T2;
         body.works = works;

@@ -231,6 +231,35 @@ def test_periodic_series_ties(ctx):
         assert got["eps"][0] == 0.0 and got["eps"][1] == 0.0
 
 
+def test_pass3_prefix_table_overflow(ctx):
+    # keys of this series are multiples of 3; the thresholds 3, 6, 12, 24 and
+    # 48 have equal mantissas, so their 21-bit prefixes share the low bits and
+    # fall in one set of the pass-3 prefix table: more than the set holds, so
+    # the series takes the slot-table lookups.  Each target sits in the middle
+    # of its threshold's run of equal keys.
+    y = synth.periodic_integer(900, 23, seed=3)
+    i, j = np.triu_indices(len(y), 1)
+    keys = np.sort(np.abs(y[i] - y[j]).astype(np.float32))
+    vals = np.array([3, 6, 12, 24, 48], np.float32)
+    assert len({int(v.view(np.uint32)) >> 10 & 4095 for v in vals}) == 1
+    rr = np.array([(np.searchsorted(keys, v, "left") + np.searchsorted(keys, v, "right")) / 2 / len(keys)
+                   for v in vals])
+    p = (1, 1, 0, 1, 2)
+    print("[parity] pass-3 prefix set overflow", flush=True)
+    got = ctx.select_thresholds(dev(y), p, rr)[0]
+    want = oracle.select(y, 1, 1, 0, 1, rr)[0]
+    assert np.array_equal(np.asarray(got, np.float32).view(np.uint32), np.asarray(want, np.float32).view(np.uint32))
+    assert np.array_equal(np.asarray(got, np.float32), vals)
+    # two of them (a set holds two) and a non-integer series take the table
+    got = ctx.select_thresholds(dev(y), p, rr[:2])[0]
+    assert np.array_equal(np.asarray(got, np.float32), vals[:2])
+    case = synth.config_small(3)
+    rr2 = np.linspace(0.01, 0.3, 12)
+    got = ctx.select_thresholds(dev(case["y"]), prm(case), rr2)[0]
+    want = oracle.select(case["y"], case["m"], case["tau"], case["norm"], case["theiler"], rr2)[0]
+    assert np.array_equal(np.asarray(got, np.float32).view(np.uint32), np.asarray(want, np.float32).view(np.uint32))
+
+
 def test_constant_series(ctx):
     y = np.full(300, 2.5, dtype=np.float32)
     case = {"name": "constant", "y": y, "m": 3, "tau": 2, "norm": 1, "theiler": 1, "lmin": 2,
