@@ -581,7 +581,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             for (const Group& g : groups) {
                 DevBufs v = view(g);
                 const int var = g.sel;
-                const uint32_t block = 512;
+                uint32_t block = 512;
                 uint32_t G = 1, ngroups = 1;
                 if (pass == 2) {
                     // pass-2 slots that fit the LDS next to the bucket table
@@ -594,7 +594,10 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                     return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass 3", K);
                 }
                 const size_t lds = select_lds_bytes(pass, K, G);
-                const int per_cu = select_blocks_per_cu(pass, var, block, lds);
+                int per_cu = select_blocks_per_cu(pass, var, block, lds);
+                // pass 2 at large K: when the bins admit one workgroup per CU,
+                // a 1024-thread one puts twice the waves on the same bins
+                if (pass == 2 && per_cu == 1) block = 1024;
                 const uint32_t grid = c->grid ? c->grid
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
                 const int t = take(ngroups);
