@@ -1,7 +1,8 @@
 """Float64 reference of the threshold-bracket network (66 -> 128 -> 128 -> 20,
 exact GELU on the hidden layers, linear output, mean-squared-error loss).
 
-TEST INFRASTRUCTURE ONLY: used to check the GPU forward pass and gradients.
+TEST INFRASTRUCTURE ONLY: used to check the GPU forward pass, gradients and
+the Adam update.
 Parameter vector layout: W1 [66][128], b1 [128], W2 [128][128], b2 [128],
 W3 [128][20], b3 [20], row-major (W[i][o] at i * O + o).
 """
@@ -79,3 +80,19 @@ def init(seed):
         else:
             parts.append(np.zeros(shape).ravel())
     return np.concatenate(parts)
+
+
+def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, "Adam: a method for stochastic
+    optimization", ICLR 2015, Algorithm 1) in float64 at step t >= 1:
+      m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2,
+      m_hat = m / (1 - b1^t),   v_hat = v / (1 - b2^t),
+      theta <- theta - lr m_hat / (sqrt(v_hat) + eps).
+    Returns (theta, m, v) as new arrays."""
+    theta = np.asarray(theta, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -70,20 +70,36 @@ def sample_keys(y, m, tau, norm, w, seed):
     return out
 
 
-def sketch(y, m, tau, norm, w, seed):
-    """(features float32[66], scale_bits) of the series."""
-    keys = sample_keys(y, m, tau, norm, w, seed)
+def bin_of(bits, scale):
+    """Sketch bin of a key bit pattern: clamp(floor((bits - scale) / 2^21)
+    + 32, 0, 63), i.e. quarter binades counted from the median's, bin 32
+    starting at the median itself (Python's >> on a negative int floors)."""
+    idx = ((int(bits) - int(scale)) >> 21) + 32
+    return min(max(idx, 0), 63)
+
+
+def features_from_keys(keys, n, m):
+    """(features float32[66], scale_bits) from the P sampled keys of a
+    series of n samples with embedding dimension m."""
+    keys = np.asarray(keys, dtype=np.float32)
+    if keys.size != P:
+        raise ValueError(f"need {P} sampled keys")
     bits = np.sort(keys.view(np.uint32).astype(np.int64))
     scale = int(bits[P // 2 - 1])
     counts = np.zeros(64, dtype=np.int64)
     for b in bits:
-        idx = ((int(b) - scale) >> 21) + 32
-        counts[min(max(idx, 0), 63)] += 1
+        counts[bin_of(b, scale)] += 1
     f = np.zeros(66, dtype=np.float32)
     f[:64] = (counts / P).astype(np.float32)
-    f[64] = np.float32(math.log2(len(y)) / 16.0)
+    f[64] = np.float32(math.log2(n) / 16.0)
     f[65] = np.float32(m / 4.0)
     return f, scale
+
+
+def sketch(y, m, tau, norm, w, seed):
+    """(features float32[66], scale_bits) of the series."""
+    keys = sample_keys(y, m, tau, norm, w, seed)
+    return features_from_keys(keys, len(y), m)
 
 
 def target_offsets(eps, scale):

@@ -209,6 +209,42 @@ def test_order_statistic_invariant():
     assert np.all(c / M >= rr - 1e-12)
 
 
+@pytest.mark.parametrize("m,tau,norm,w,kind", [(1, 1, 0, 1, "integer"), (1, 1, 1, 1, "integer"),
+                                               (3, 5, 1, 1, "normal"), (2, 3, 0, 2, "normal"),
+                                               (3, 2, 1, 3, "integer")])
+def test_count_strict_and_inclusive_match_numpy(m, tau, norm, w, kind):
+    """#{key < v} and #{key <= v} (the two sides of the order-statistic
+    bracket #{key < eps} < k <= #{key <= eps} that pins a threshold at any
+    size) against numpy counts over the brute-force key list: values equal
+    to keys (ties: integer series make many equal keys), values between
+    consecutive distinct keys, 0, +inf and values outside the key range."""
+    r = rng(31 + m + w)
+    n = 900
+    if kind == "integer":
+        y = r.integers(0, 12, n).astype(np.float32)
+    else:
+        y = r.standard_normal(n).astype(np.float32)
+    keys = np_keys_diag_major(y, m, tau, norm, w)
+    u = np.unique(keys)
+    if kind == "integer":
+        assert len(u) < len(keys) // 100             # many ties
+    pick = u[r.choice(len(u), 12, replace=False)]
+    between = [np.nextafter(u[i], u[i + 1]) for i in r.choice(len(u) - 1, 8, replace=False)]
+    vals = np.concatenate([pick, np.array(between, dtype=np.float32), u[:1], u[-1:],
+                           np.array([0.0, np.inf, u[-1] * 2 + 1, np.float32(1e-30)], dtype=np.float32)])
+    lt, le = oracle.count(y, m, tau, norm, w, vals)
+    want_lt = np.array([np.sum(keys < v) for v in vals], dtype=np.uint64)
+    want_le = np.array([np.sum(keys <= v) for v in vals], dtype=np.uint64)
+    np.testing.assert_array_equal(lt, want_lt)
+    np.testing.assert_array_equal(le, want_le)
+    # at a key value the two counts differ by its multiplicity (> 1 for ties)
+    mult = le[:12] - lt[:12]
+    assert np.all(mult >= 1)
+    if kind == "integer":
+        assert np.all(mult > 1)
+    assert lt[-4] == 0 and le[-3] == len(keys)       # v = 0 (no key below 0), v = +inf
+
+
 def test_select_ties_all_equal():
     y = np.full(50, 3.25, dtype=np.float32)
     eps, k, c = oracle.select(y, 2, 3, 1, 1, [0.01, 0.5, 1.0])

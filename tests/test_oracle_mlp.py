@@ -40,3 +40,32 @@ def test_backprop_matches_finite_differences():
         tm = theta.copy(); tm[i] -= h
         fd = (mlp.loss(tp, X, T) - mlp.loss(tm, X, T)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, i
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments the bias corrections cancel at t = 1: m_hat = g and
+    v_hat = g^2, so the step is -lr g / (|g| + eps) element by element (a
+    swapped b1/b2, a missing bias correction or a wrong sign changes it)."""
+    rng = np.random.default_rng(21)
+    theta = rng.normal(0, 1, 50)
+    g = rng.normal(0, 1, 50) * np.logspace(-9, 2, 50)
+    z = np.zeros(50)
+    lr = 3e-3
+    t1, m1, v1 = mlp.adam_step(theta, g, z, z, 1, lr)
+    np.testing.assert_allclose(t1, theta - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_second_step_hand_worked():
+    """Scalar case worked by hand: g1 = 1, g2 = 0.5, lr = 0.1, from zero.
+    Step 1: theta1 = -0.1 / (1 + 1e-8).  Step 2: m2 = 0.9 * 0.1 + 0.1 * 0.5
+    = 0.14, v2 = 0.999 * 0.001 + 0.001 * 0.25 = 0.001249; m_hat = 0.14 / 0.19
+    = 14/19, v_hat = 0.001249 / 0.001999 = 1249/1999, so theta2 = theta1 -
+    0.1 * (14/19) / (sqrt(1249/1999) + 1e-8)."""
+    th, m, v = mlp.adam_step([0.0], [1.0], [0.0], [0.0], 1, 0.1)
+    assert abs(th[0] + 0.1 / (1 + 1e-8)) < 1e-16
+    th, m, v = mlp.adam_step(th, [0.5], m, v, 2, 0.1)
+    assert abs(m[0] - 0.14) < 1e-15 and abs(v[0] - 0.001249) < 1e-14 * 0.001249
+    want = -0.1 / (1 + 1e-8) - 0.1 * (14 / 19) / (math.sqrt(1249 / 1999) + 1e-8)
+    assert abs(th[0] - want) < 1e-15

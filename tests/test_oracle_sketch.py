@@ -1,4 +1,7 @@
 """Pins for the sketch oracle (CPU only)."""
+import json
+import os
+
 import numpy as np
 
 import oracle
@@ -42,3 +45,32 @@ def test_target_offsets_sign_and_scale():
     scale = int(np.float32(1.0).view(np.uint32))
     t = sketch.target_offsets([2.0, 0.5, 1.0], scale)
     np.testing.assert_array_equal(t, np.array([1.0, -1.0, 0.0], np.float32))
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "sketch_bins.json")
+
+
+def test_sketch_binning_hand_derived():
+    """Bins, scale and features of a hand-built key multiset: each value's
+    bin is derived by hand from its bit pattern in the fixture, chosen so
+    that a shift of 20 instead of 21, an offset of 31 instead of 32, a
+    rounding toward zero instead of a floor, the other median or a wrong
+    clamp each change some bin."""
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    keys = []
+    for e in g["keys"]:
+        v = np.float32(float(e["value"]))
+        assert int(v.view(np.uint32)) == int(e["bits"], 16), e
+        keys += [v] * e["count"]
+    keys = np.array(keys, dtype=np.float32)
+    np.random.default_rng(0).shuffle(keys)          # the sample comes in pair order
+    f, scale = sketch.features_from_keys(keys, g["n"], g["m"])
+    assert scale == int(g["scale"], 16)
+    want = np.zeros(64, dtype=np.float32)
+    for b, c in g["bins"].items():
+        want[int(b)] = np.float32(c / 4096)
+    np.testing.assert_array_equal(f[:64], want)
+    assert f[64] == np.float32(g["feature_64"]) and f[65] == np.float32(g["feature_65"])
+    for e in g["keys"]:
+        assert sketch.bin_of(int(e["bits"], 16), scale) in [int(b) for b in g["bins"]]
