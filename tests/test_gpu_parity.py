@@ -72,9 +72,11 @@ def test_medium_systems_reduced_length(ctx, idx):
     check_case(ctx, synth.config_medium(n=2500)[idx])
 
 
-@pytest.mark.parametrize("idx", [0, 7, 12])
+@pytest.mark.parametrize("idx", range(15))
 def test_medium_systems_full_length(ctx, idx):
-    """Sine, logistic and Lorenz at N=10^4 (Euclidean; m=3, tau=5 for Lorenz)."""
+    """Every series of the N=10^4 configuration at full length: sine,
+    logistic and Lorenz at SNR 20, 10, 0, -10, -20 dB (Euclidean; m=3, tau=5
+    for Lorenz, m=1 otherwise), K=20, against the oracle's sort path."""
     check_case(ctx, synth.config_medium()[idx])
 
 
@@ -105,14 +107,54 @@ def test_large_bench_batch(ctx):
             k = oracle.rank(c["rr"][r], M)
             assert lt[i] < k <= le[i]
             assert le[i] == got["count"][s][r]
-        print(f"[parity] {c['name']} oracle lines at {len(targets)} thresholds", flush=True)
-        lin = oracle.lines(c["y"], 3, 5, 1, 1, 2, eps)
+        nv = oracle.num_vectors(100_000, 3, 5)
+        print(f"[parity] {c['name']} oracle lines and histograms at {len(targets)} thresholds", flush=True)
+        lin = oracle.lines(c["y"], 3, 5, 1, 1, 2, eps, hist_len=nv + 1)
         assert np.array_equal(lin["count"], got["count"][s][targets])
         assert np.array_equal(lin["rr"], got["rr"][s][targets])
         assert np.array_equal(lin["det"], got["det"][s][targets])
+        # the full line-length histogram at the selected thresholds, every
+        # length kept, element by element (Eq. 4's P(l) at full size)
+        print(f"[parity] {c['name']} GPU histograms at {len(targets)} thresholds", flush=True)
+        full = ctx.det_curve(dev(c["y"]), prm(c), eps, hist_len=nv + 1)
+        assert full["hist"].shape == lin["hist"].shape
+        assert np.array_equal(full["hist"], lin["hist"])
+        assert np.array_equal(full["count"], lin["count"])
+        assert np.array_equal(full["det"], lin["det"])
     # the averaged DET is the left-to-right mean of the 20 DET values
     for s in range(2):
         assert got["det_mean"][s] == sum(got["det"][s].tolist()) / 20
+
+
+def test_ensemble_slice_one_batch(ctx):
+    """A seeded 60-series slice of the 600-series ensemble (both embedding
+    groups: m = 1 for sine and logistic, m = 3 / tau = 5 for Lorenz, and the
+    ensemble's longest series) selected and swept in one rqa_batch call,
+    every series against the oracle's whole path."""
+    import concurrent.futures as cf
+    import torch
+    cases = synth.config_batch()
+    lengths = np.array([len(c["y"]) for c in cases])
+    rng = np.random.default_rng(2024)
+    pick = set(rng.choice(len(cases), 59, replace=False).tolist())
+    pick.add(int(np.argmax(lengths)))
+    while len(pick) < 60:
+        pick.add(int(rng.integers(len(cases))))
+    sel = [cases[i] for i in sorted(pick)]
+    assert {c["m"] for c in sel} == {1, 3}
+    assert max(len(c["y"]) for c in sel) == lengths.max()
+    offs = np.concatenate([[0], np.cumsum([len(c["y"]) for c in sel])]).astype(np.uint64)
+    concat = torch.from_numpy(np.concatenate([c["y"] for c in sel])).to("cuda:0")
+    rr = np.stack([c["rr"] for c in sel])
+    print(f"[parity] ensemble slice: 60 series, longest {lengths.max()}", flush=True)
+    got = ctx.batch(concat, offs, [prm(c) for c in sel], rr)
+    with cf.ThreadPoolExecutor(8) as ex:
+        wants = list(ex.map(oracle_run, sel))
+    for s_, (c, want) in enumerate(zip(sel, wants)):
+        one = {key: got[key][s_] for key in ("eps", "count", "rr", "det")}
+        one["k"] = want["k"]
+        one["det_mean"] = got["det_mean"][s_]
+        assert_run_equal(one, want, c["name"])
 
 
 # ---------------------------------------------------------------- golden plots
