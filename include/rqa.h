@@ -164,6 +164,18 @@ rqa_status rqa_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const ui
  * passes 1-3.  Returns the number of entries written. */
 int rqa_phase_times(rqa_ctx *ctx, double *times_out, int n_out);
 
+/* Measured VALU issue rate of the context's GPU, the denominator of the
+ * library's roofline (its kernels are bound by vector-ALU issue and LDS, not
+ * by HBM: the input is O(n) bytes and every count stays in LDS or L2).
+ * Every lane of 8 workgroups of 256 threads per CU runs 16 independent
+ * dependency chains of one instruction:
+ *   kind 0: v_add_f32 (32-bit float add), 1: v_add_u32 (32-bit integer add),
+ *   2: v_max_u32 (32-bit integer max).
+ * *lane_ops_per_s receives executed lane-operations per second of the
+ * fastest of 8 timed launches (HIP events on the context stream);
+ * *ms_out (or NULL) that launch's time.  Uses the context's scratch. */
+rqa_status rqa_valu_rate(rqa_ctx *ctx, uint32_t kind, double *lane_ops_per_s, double *ms_out);
+
 /* Enable (1) or disable (0) per-phase HIP-event timing on the context. */
 rqa_status rqa_set_timing(rqa_ctx *ctx, int enable);
 

@@ -15,7 +15,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librqa.so")
-SOURCES = ["kernels.hip", "mlp.hip", "capi.hip"]
+SOURCES = ["kernels.hip", "mlp.hip", "probe.hip", "capi.hip"]
 ARCH = os.environ.get("RQA_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -28,11 +28,27 @@ FLAGS = [
 
 
 def build(verbose=False, out=None, defines=()):
-    """Compile librqa.so (or `out`); `defines` are extra -D options."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile librqa.so (or `out`); `defines` are extra -D options.  The
+    sources compile to objects in parallel (no device code crosses a source
+    file: every kernel is launched from its own file), then link."""
     lib = out or LIB
     tmp = lib + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + ["-o", tmp] + srcs
+    objdir = os.path.join(os.path.dirname(lib), "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    defs = ["-D" + d for d in defines]
+    procs, objs = [], []
+    for name in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(name)[0] + ".o")
+        cmd = [HIPCC] + compile_flags + defs + ["-c", "-o", obj, os.path.join(CSRC, name)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1139,6 +1139,42 @@ int rqa_phase_times(rqa_ctx* c, double* out, int n)
     return k;
 }
 
+rqa_status rqa_valu_rate(rqa_ctx* c, uint32_t kind, double* lane_ops_per_s, double* ms_out)
+{
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (kind > 2) return fail(RQA_ERR_INVALID_ARG, "probe kind %u outside 0..2", kind);
+    if (!lane_ops_per_s) return fail(RQA_ERR_INVALID_ARG, "lane_ops_per_s is NULL");
+    // 32 waves per CU (8 per SIMD) with 16 independent chains each keep every
+    // SIMD's issue port busy; 8 launches of a few milliseconds, the fastest counts
+    const uint32_t blocks = (uint32_t)c->num_cu * 8;
+    const uint32_t iters = 2048;
+    if ((st = ensure_pool(c, sizeof(uint32_t) * valu_probe_threads(blocks)))) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RQA_ERR_DEVICE, "hipEventCreate failed");
+    }
+    double best = 1e300;
+    hipError_t e = launch_valu_probe(c->stream, (int)kind, blocks, iters, (uint32_t*)c->pool);  // warm-up
+    for (int rep = 0; rep < 8 && e == hipSuccess; ++rep) {
+        float ms = 0.f;
+        e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = launch_valu_probe(c->stream, (int)kind, blocks, iters, (uint32_t*)c->pool);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms > 0.f) best = std::min(best, (double)ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(RQA_ERR_DEVICE, "VALU probe failed: %s", hipGetErrorString(e));
+    *lane_ops_per_s = valu_probe_lane_ops(blocks, iters) / (best * 1e-3);
+    if (ms_out) *ms_out = best;
+    return RQA_OK;
+}
+
 rqa_status rqa_set_shape(rqa_ctx* c, uint32_t segment, uint32_t chunk_tiles)
 {
     if (!c) return fail(RQA_ERR_INVALID_ARG, "context is NULL");

@@ -230,4 +230,10 @@ int select_blocks_per_cu(int pass, int variant, uint32_t block, size_t lds);
 int sweep_blocks_per_cu(int variant, bool ranges, uint32_t block, size_t lds);
 hipError_t set_kernel_lds_limits(size_t max_dyn_lds);
 
+// VALU issue-rate probe (probe.hip): kind 0 v_add_f32, 1 v_add_u32,
+// 2 v_max_u32; `out` holds valu_probe_threads(blocks) words.
+hipError_t launch_valu_probe(hipStream_t st, int kind, uint32_t blocks, uint32_t iters, uint32_t* out);
+uint64_t valu_probe_threads(uint32_t blocks);
+double valu_probe_lane_ops(uint32_t blocks, uint32_t iters);
+
 }  // namespace rqa

@@ -58,6 +58,7 @@ SIGNATURES = {
     "rqa_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up]),
     "rqa_phase_times": (_i32, [_vp, _dp, _i32]),
     "rqa_set_timing": (_i32, [_vp, _i32]),
+    "rqa_valu_rate": (_i32, [_vp, _u32, _dp, _dp]),
     "rqa_set_shape": (_i32, [_vp, _u32, _u32]),
     "rqa_set_grid": (_i32, [_vp, _u32]),
     "rqa_autotune": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
@@ -153,6 +154,16 @@ def rqa_destroy(ctx):
 
 def rqa_set_timing(ctx, enable=True):
     _check(load().rqa_set_timing(ctx, 1 if enable else 0))
+
+
+VALU_PROBES = {"v_add_f32": 0, "v_add_u32": 1, "v_max_u32": 2}
+
+
+def rqa_valu_rate(ctx, kind):
+    """Measured VALU rate of one instruction class: (lane-ops/s, ms)."""
+    rate, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(load().rqa_valu_rate(ctx, VALU_PROBES.get(kind, kind), ctypes.byref(rate), ctypes.byref(ms)))
+    return rate.value, ms.value
 
 
 def rqa_phase_times(ctx):
@@ -434,6 +445,9 @@ class Context:
 
     def set_timing(self, enable=True):
         rqa_set_timing(self.ctx, enable)
+
+    def valu_rate(self, kind):
+        return rqa_valu_rate(self.ctx, kind)
 
     def phase_times(self):
         return rqa_phase_times(self.ctx)
