@@ -153,6 +153,30 @@ rqa_status rqa_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const ui
                      float *eps_out, double *rr_out, double *det_out, double *det_mean_out,
                      uint64_t *count_out);
 
+/* rqa_batch without any allocation, for callers that cannot allocate memory
+ * on the device: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, results and errors as in
+ * rqa_batch (results are bit-identical), except:
+ *   - flags: RQA_SEL_PLAIN, RQA_SEL_SAMPLE or RQA_SEL_WINDOW;
+ *     RQA_SEL_LEARNED returns RQA_ERR_UNSUPPORTED.
+ *   - Device scratch comes from a static area of RQA_STATIC_SCRATCH_BYTES
+ *     per GPU, which the GPU holds from the first rqa_create on it until the
+ *     process ends.  A call whose scratch would not fit (it grows with S and
+ *     K: about 0.7 MB per series at K = 20 with plain selection, 3 MB with
+ *     RQA_SEL_SAMPLE) returns RQA_ERR_NOMEM before any work, and
+ *     rqa_last_error() gives the bytes needed.
+ *   - No device or pinned host memory is allocated; host staging uses the
+ *     context's ordinary host memory.
+ *   - Every call on one GPU shares that GPU's area and leaves its contents
+ *     behind (each call clears what it needs): calls that overlap on one GPU,
+ *     from any context or thread, race and must be serialised by the
+ *     caller. */
+#define RQA_STATIC_SCRATCH_BYTES (64u << 20)
+rqa_status rqa_batch_static(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
+                            const rqa_params *p, const double *rr, uint32_t K, uint32_t flags,
+                            float *eps_out, double *rr_out, double *det_out, double *det_mean_out,
+                            uint64_t *count_out);
+
 /* Per-phase device times of the last computing call (select, det curve,
  * run, batch, sketch), in milliseconds, measured with HIP events on the
  * context stream when timing is enabled (rqa_set_timing) and summed over

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,40 @@ rqa_status fail(rqa_status st, const char* fmt, ...)
         if (e_ != hipSuccess)                                                                  \
             return fail(RQA_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
     } while (0)
+
+// Device scratch of rqa_batch_static, for callers that cannot allocate
+// device memory.  Each GPU holds its own copy of this array from the first
+// use of the library on it until the process ends.  Host code never passes
+// the array's name to a kernel or a copy: it holds a host-side stand-in, not
+// a device address.  The device address of each GPU's copy is resolved once
+// per device with hipGetSymbolAddress (resolve_static_scratch, called by
+// rqa_create) and only that address is used.
+constexpr size_t STATIC_SCRATCH_BYTES = RQA_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `device`'s copy of the static scratch; the device must
+// be current.
+rqa_status resolve_static_scratch(int device, void** out)
+{
+    if (device < 0 || device >= MAX_DEVICES)
+        return fail(RQA_ERR_UNSUPPORTED, "device %d: the static scratch serves devices 0..%d", device, MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(RQA_ERR_DEVICE, "hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return RQA_OK;
+}
 
 enum Phase { PH_P1 = 0, PH_P2 = 1, PH_P3 = 2, PH_SWEEP = 3, PH_OTHER = 4, PH_HIST = 5, PH_N = 6 };
 
@@ -92,6 +127,13 @@ struct rqa_ctx {
     // host staging (pinned)
     void* host = nullptr;
     size_t host_bytes = 0;
+    // rqa_batch_static: this device's copy of the static scratch area (its
+    // device address, resolved once per device), and, while such a call
+    // runs, use_static = true: the call's device scratch comes from that
+    // area and its host staging from static_host (ordinary host memory)
+    void* static_dev = nullptr;
+    bool use_static = false;
+    std::vector<unsigned char> static_host;
     // timing
     bool timing = false;
     hipEvent_t ev[2 * PH_N * 8] = {};
@@ -451,9 +493,18 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_delta = window ? carve(sizeof(float) * MLP_OUT) : 0;
     if (window && window_lds_bytes(1) > c->max_lds)
         return fail(RQA_ERR_UNSUPPORTED, "the window pass needs %zu bytes of LDS per workgroup", window_lds_bytes(1));
-    rqa_status st = ensure_pool(c, off);
-    if (st) return st;
-    char* pool = (char*)c->pool;
+    rqa_status st = RQA_OK;
+    char* pool = nullptr;
+    if (c->use_static) {
+        // rqa_batch_static: the fixed device area; nothing is allocated
+        if (off > STATIC_SCRATCH_BYTES)
+            return fail(RQA_ERR_NOMEM, "this call needs %zu bytes of device scratch; the static area holds %zu "
+                        "(fewer series or targets per call, or rqa_batch)", off, STATIC_SCRATCH_BYTES);
+        pool = (char*)c->static_dev;
+    } else {
+        if ((st = ensure_pool(c, off))) return st;
+        pool = (char*)c->pool;
+    }
     DevBufs all;
     all.sd = (SeriesDesc*)(pool + o_sd);
     all.work = (SeriesWork*)(pool + o_work);
@@ -475,13 +526,22 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     // host staging: descriptors + work (in), work (out), sketch features (out)
     const size_t hs_sd = sizeof(SeriesDesc) * S, hs_work = sizeof(SeriesWork) * S;
     const size_t hs_feat = (job.mode & MODE_SKETCH) ? sizeof(float) * S * SKETCH_FEATURES : 0;
-    st = ensure_host(c, hs_sd + 2 * hs_work + hs_feat + sizeof(float) * MLP_OUT);
-    if (st) return st;
-    SeriesDesc* h_sd = (SeriesDesc*)c->host;
-    SeriesWork* h_work = (SeriesWork*)((char*)c->host + hs_sd);
-    SeriesWork* h_out = (SeriesWork*)((char*)c->host + hs_sd + hs_work);
-    float* h_feat = (float*)((char*)c->host + hs_sd + 2 * hs_work);
-    float* h_delta = (float*)((char*)c->host + hs_sd + 2 * hs_work + hs_feat);
+    const size_t hs_all = hs_sd + 2 * hs_work + hs_feat + sizeof(float) * MLP_OUT;
+    char* hbase = nullptr;
+    if (c->use_static) {
+        // ordinary host memory (no pinned allocation); the copies below then
+        // stage through the runtime, and the call synchronises before return
+        if (c->static_host.size() < hs_all) c->static_host.resize(hs_all);
+        hbase = (char*)c->static_host.data();
+    } else {
+        if ((st = ensure_host(c, hs_all))) return st;
+        hbase = (char*)c->host;
+    }
+    SeriesDesc* h_sd = (SeriesDesc*)hbase;
+    SeriesWork* h_work = (SeriesWork*)(hbase + hs_sd);
+    SeriesWork* h_out = (SeriesWork*)(hbase + hs_sd + hs_work);
+    float* h_feat = (float*)(hbase + hs_sd + 2 * hs_work);
+    float* h_delta = (float*)(hbase + hs_sd + 2 * hs_work + hs_feat);
     std::memcpy(h_delta, c->bracket_delta, sizeof(float) * MLP_OUT);
     if (window && job.sel == 1 && !c->has_model)
         return fail(RQA_ERR_INVALID_ARG, "RQA_SEL_LEARNED needs a network (rqa_mlp_init / rqa_mlp_set_params)");
@@ -1079,8 +1139,12 @@ rqa_status rqa_create(rqa_ctx** out, int device, void* hip_stream)
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(RQA_ERR_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+    void* static_dev = nullptr;
+    rqa_status sst = resolve_static_scratch(device, &static_dev);
+    if (sst) return sst;
     rqa_ctx* c = new rqa_ctx();
     c->device = device;
+    c->static_dev = static_dev;
     c->num_cu = prop.multiProcessorCount;
     c->max_lds = std::max<size_t>(prop.sharedMemPerBlock, 65536);
     if (prop.maxSharedMemoryPerMultiProcessor > 0)
@@ -1318,6 +1382,24 @@ rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t
     }
     for (uint32_t s = 0; s < S; ++s) det_mean_out[s] = job.det_mean[s];
     return RQA_OK;
+}
+
+rqa_status rqa_batch_static(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,
+                            const rqa_params* p, const double* rr, uint32_t K, uint32_t flags, float* eps_out,
+                            double* rr_out, double* det_out, double* det_mean_out, uint64_t* count_out)
+{
+    if (c) reset_phases(c);
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    int sel = 0;
+    if ((st = check_flags_select(flags, &sel))) return st;
+    // the network's activations live in allocated memory
+    if (sel == 1) return fail(RQA_ERR_UNSUPPORTED, "rqa_batch_static takes RQA_SEL_PLAIN, RQA_SEL_SAMPLE or RQA_SEL_WINDOW");
+    if (!c->static_dev) return fail(RQA_ERR_DEVICE, "the static scratch of device %d is not resolved", c->device);
+    c->use_static = true;
+    st = rqa_batch(c, S, concat, offsets, p, rr, K, flags, eps_out, rr_out, det_out, det_mean_out, count_out);
+    c->use_static = false;
+    return st;
 }
 
 rqa_status rqa_autotune(rqa_ctx* c, const float* series, uint64_t n, const rqa_params* p, const double* rr, uint32_t K,

@@ -56,6 +56,7 @@ SIGNATURES = {
     "rqa_det_curve": (_i32, [_vp, _vp, _u64, _pp, _fp, _u32, _u32, _up, _dp, _dp, _dp, _up, _u64]),
     "rqa_run": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, _u32, _fp, _up, _up, _dp, _dp, _dp]),
     "rqa_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up]),
+    "rqa_batch_static": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up]),
     "rqa_phase_times": (_i32, [_vp, _dp, _i32]),
     "rqa_set_timing": (_i32, [_vp, _i32]),
     "rqa_valu_rate": (_i32, [_vp, _u32, _dp, _dp]),
@@ -385,7 +386,7 @@ def rqa_run(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
     return {"eps": eps, "k": k, "count": cnt, "rr": rro, "det": det, "det_mean": float(dm[0])}
 
 
-def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN, _entry="rqa_batch"):
     """S series back to back in one device tensor.  offsets: S+1 element
     offsets; params: S parameter sets; rr: (S, K) targets.  Returns dict of
     (S, K) arrays eps, rr, det, count and det_mean (S,)."""
@@ -402,10 +403,20 @@ def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
     det = np.zeros((S, K), np.float64)
     cnt = np.zeros((S, K), np.uint64)
     dm = np.zeros(S, np.float64)
-    _check(load().rqa_batch(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, _p(rrt, ctypes.c_double), K, flags,
-                            _p(eps, ctypes.c_float), _p(rro, ctypes.c_double), _p(det, ctypes.c_double),
-                            _p(dm, ctypes.c_double), _p(cnt, ctypes.c_uint64)))
+    fn = getattr(load(), _entry)
+    _check(fn(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, _p(rrt, ctypes.c_double), K, flags,
+              _p(eps, ctypes.c_float), _p(rro, ctypes.c_double), _p(det, ctypes.c_double),
+              _p(dm, ctypes.c_double), _p(cnt, ctypes.c_uint64)))
     return {"eps": eps, "rr": rro, "det": det, "det_mean": dm, "count": cnt}
+
+
+RQA_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def rqa_batch_static(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+    """rqa_batch with device scratch from the library's static area: the call
+    allocates no device memory (see include/rqa.h)."""
+    return rqa_batch(ctx, concat, offsets, params, rr, flags, _entry="rqa_batch_static")
 
 
 class Context:
@@ -442,6 +453,9 @@ class Context:
 
     def batch(self, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
         return rqa_batch(self.ctx, concat, offsets, params, rr, flags)
+
+    def batch_static(self, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+        return rqa_batch_static(self.ctx, concat, offsets, params, rr, flags)
 
     def set_timing(self, enable=True):
         rqa_set_timing(self.ctx, enable)
