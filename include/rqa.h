@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define RQA_MAX_K 128
-#define RQA_MAX_HIST_K 32          /* distinct thresholds of one full-histogram call */
+#define RQA_MAX_HIST_K 32          /* thresholds of one full-histogram pass over the pairs */
 #define RQA_MAX_HIST_LEN (1u << 24) /* entries per full-histogram row */
 
 typedef struct rqa_ctx rqa_ctx;
@@ -75,14 +75,18 @@ typedef struct {
     uint32_t lmin;
 } rqa_params;
 
-/* flags */
+/* flags.  Every selection method gives the same exact thresholds; they
+ * differ in the number of passes over the pairs. */
 enum {
-    RQA_SEL_PLAIN = 0,   /* exact selection: three radix passes over all pairs */
+    RQA_SEL_AUTO = 0,    /* exact selection, the method picked by the library: RQA_SEL_SAMPLE for calls
+                            of at least 2^29 pairs in all (where its set-up pays), else RQA_SEL_PLAIN */
     RQA_SEL_LEARNED = 1, /* exact selection inside a key window the network predicts (two passes);
                             series with a target outside the window fall back to RQA_SEL_PLAIN */
     RQA_FULL_HIST = 2,   /* rqa_det_curve only: also return the full line-length histogram P(l) */
     RQA_SEL_SAMPLE = 4,  /* as RQA_SEL_LEARNED with the window from sketch-sample quantiles (no network) */
-    RQA_SEL_WINDOW = 8   /* as RQA_SEL_LEARNED with the window set by rqa_set_window (for tests) */
+    RQA_SEL_WINDOW = 8,  /* as RQA_SEL_LEARNED with the window set by rqa_set_window (for tests) */
+    RQA_SEL_PLAIN = 16   /* exact selection by radix passes over all pairs (three; the line sweep
+                            takes the third when DET is asked for) */
 };
 
 /* Create a context on HIP device `device`.  hip_stream is a hipStream_t on
@@ -99,7 +103,8 @@ void rqa_destroy(rqa_ctx *ctx);
  * the same exact thresholds; they differ in the number of passes.
  *   series_dev: n float32 samples (device).
  *   rr: K targets in (0, 1] (host), any order, repeats allowed.
- *   flags: RQA_SEL_PLAIN or RQA_SEL_LEARNED.
+ *   flags: one selection method (RQA_SEL_AUTO, RQA_SEL_PLAIN, RQA_SEL_SAMPLE,
+ *     RQA_SEL_LEARNED or RQA_SEL_WINDOW).
  *   eps_out[K]: eps_r = the k_r-th smallest key (host).
  *   k_out[K] (or NULL): k_r.   count_out[K] (or NULL): #{key <= eps_r}.
  * Outputs follow the order of rr. */
@@ -124,9 +129,9 @@ rqa_status rqa_select_thresholds(rqa_ctx *ctx, const float *series_dev, uint64_t
  *     line, and DET_r = sum_{l >= lmin} l P_r(l) / C_r.
  *   hist_len: 1 .. RQA_MAX_HIST_LEN.  Without the flag hist_out must be NULL
  *     and hist_len 0.
- *   Limits of the full histogram: at most RQA_MAX_HIST_K distinct values
- *   among eps and fewer than 2^24 - 1 embedded vectors, else
- *   RQA_ERR_UNSUPPORTED. */
+ *   Limits of the full histogram: fewer than 2^24 - 1 embedded vectors,
+ *   else RQA_ERR_UNSUPPORTED.  One histogram pass over the pairs takes up to
+ *   RQA_MAX_HIST_K thresholds; more run as several passes in the same call. */
 rqa_status rqa_det_curve(rqa_ctx *ctx, const float *series_dev, uint64_t n,
                          const rqa_params *p, const float *eps, uint32_t K, uint32_t flags,
                          uint64_t *count_out, double *rr_out, double *det_out,
@@ -153,11 +158,29 @@ rqa_status rqa_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const ui
                      float *eps_out, double *rr_out, double *det_out, double *det_mean_out,
                      uint64_t *count_out);
 
+/* rqa_batch plus the full diagonal line-length histogram P_r(l) at every
+ * selected threshold, in the same call: the paper derives DET, the average
+ * line length L and the longest line L_max from this one histogram
+ * (Technical implementation on a GPU) and proposes averaging those measures
+ * over the RR set like DET (Averaged RQA section).
+ *   Arguments and outputs as in rqa_batch, plus
+ *   hist_out[S * K * hist_len] (host): series s, target r at
+ *     hist_out + (s * K + r) * hist_len, rows as rqa_det_curve returns them;
+ *   hist_len: 1 .. RQA_MAX_HIST_LEN.
+ * The histogram takes ceil(K / RQA_MAX_HIST_K) passes over the pairs after
+ * the selection.  Series with 2^24 - 1 or more embedded vectors give
+ * RQA_ERR_UNSUPPORTED.  rqa_line_measures turns the rows into L and L_max,
+ * rqa_averaged_det (a running mean) into their averaged curves. */
+rqa_status rqa_batch_hist(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
+                          const rqa_params *p, const double *rr, uint32_t K, uint32_t flags,
+                          float *eps_out, double *rr_out, double *det_out, double *det_mean_out,
+                          uint64_t *count_out, uint64_t *hist_out, uint64_t hist_len);
+
 /* rqa_batch without any allocation, for callers that cannot allocate memory
  * on the device: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  Arguments, results and errors as in
  * rqa_batch (results are bit-identical), except:
- *   - flags: RQA_SEL_PLAIN, RQA_SEL_SAMPLE or RQA_SEL_WINDOW;
+ *   - flags: RQA_SEL_AUTO, RQA_SEL_PLAIN, RQA_SEL_SAMPLE or RQA_SEL_WINDOW;
  *     RQA_SEL_LEARNED returns RQA_ERR_UNSUPPORTED.
  *   - Device scratch comes from a static area of RQA_STATIC_SCRATCH_BYTES
  *     per GPU, which the GPU holds from the first rqa_create on it until the

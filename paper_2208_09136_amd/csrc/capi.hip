@@ -341,10 +341,22 @@ struct Job {
     std::vector<uint8_t> hit;        // S*K, window selection: target resolved in the window
     uint32_t hist_len = 0;           // histogram mode: entries per row (length 0 .. hist_len-1)
     uint32_t hist_kp = 0;            // histogram mode: largest number of distinct thresholds
-    uint64_t* hist_dst = nullptr;    // histogram mode: host rows S*K*hist_len, P_r(l), caller order
+    uint64_t* hist_dst = nullptr;    // histogram mode: host rows P_r(l), caller order: series s's K rows
+                                     // of hist_len entries start at hist_dst + s * hist_series_stride
+    size_t hist_series_stride = 0;   // 0: K * hist_len (rows of consecutive series back to back)
 };
 
 rqa_status ensure_acts(rqa_ctx* c, uint32_t B, MlpActs& a);
+
+// Pass-2 slots (targets counted per launch) that fit the LDS next to the
+// bucket table; false if not even one does.
+bool pass2_slots(const rqa_ctx* c, uint32_t K, uint32_t* G)
+{
+    const size_t fixed = select_lds_bytes(2, K, 0);
+    const size_t room = c->max_lds > fixed ? c->max_lds - fixed : 0;
+    *G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4));
+    return *G != 0;
+}
 
 // Runs selection and/or sweep for every series of the job.
 rqa_status run_job(rqa_ctx* c, Job& job)
@@ -431,6 +443,16 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         d.f_logn = (float)(std::log2((double)z.n) / 16.0);
         d.f_m = (float)((double)z.p.m / 4.0);
         maxn = std::max<uint32_t>(maxn, (uint32_t)z.n);
+    }
+    // pass 2 of plain selection takes 1024-thread workgroups where its bins
+    // admit one workgroup per CU (large K); a chunk then needs a tile for each
+    // of their 16 waves
+    if ((job.mode & MODE_SELECT) && job.sel == 0) {
+        uint32_t G = 0;
+        const bool fits = pass2_slots(c, K, &G);
+        for (const Group& g : groups)
+            if (fits && select_blocks_per_cu(2, g.sel, 512, select_lds_bytes(2, K, G)) == 1)
+                CT = std::max<uint32_t>(CT, 1024 / TILE_W);
     }
     // The window pass flushes WIN_BINS fine bins (nearly all non-zero) each
     // time a workgroup moves to another series: give windowed jobs chunks
@@ -644,11 +666,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                 uint32_t block = 512;
                 uint32_t G = 1, ngroups = 1;
                 if (pass == 2) {
-                    // pass-2 slots that fit the LDS next to the bucket table
-                    const size_t fixed = select_lds_bytes(2, K, 0);
-                    const size_t room = c->max_lds > fixed ? c->max_lds - fixed : 0;
-                    G = (uint32_t)std::min<size_t>(K, room / (SEL_N2 * 4));
-                    if (G == 0) return fail(RQA_ERR_UNSUPPORTED, "pass 2 does not fit the LDS");
+                    if (!pass2_slots(c, K, &G)) return fail(RQA_ERR_UNSUPPORTED, "pass 2 does not fit the LDS");
                     ngroups = (K + G - 1) / G;
                 } else if (pass == 3 && select_lds_bytes(3, K, 0) > c->max_lds) {
                     return fail(RQA_ERR_UNSUPPORTED, "K=%u does not fit the LDS of pass 3", K);
@@ -727,8 +745,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         // rows straight into the caller's buffer, series back in caller order
         if (!job.hist_dst) return fail(RQA_ERR_INVALID_ARG, "histogram destination is NULL");
         const size_t rows = (size_t)K * job.hist_len;
+        const size_t stride = job.hist_series_stride ? job.hist_series_stride : rows;
         for (uint32_t i = 0; i < S; ++i)
-            HIP_TRY(hipMemcpyAsync(job.hist_dst + (size_t)order[i] * rows, (uint64_t*)(pool + o_hout) + (size_t)i * rows,
+            HIP_TRY(hipMemcpyAsync(job.hist_dst + (size_t)order[i] * stride, (uint64_t*)(pool + o_hout) + (size_t)i * rows,
                                    sizeof(uint64_t) * rows, hipMemcpyDeviceToHost, sm));
     }
     HIP_TRY(hipStreamSynchronize(sm));
@@ -807,15 +826,40 @@ rqa_status check_k(uint32_t K)
     return RQA_OK;
 }
 
+// Selection method of the flags: 0 plain radix passes, 1 network window,
+// 2 sample window, 3 caller window, -1 automatic (resolve_method).
 rqa_status check_flags_select(uint32_t flags, int* sel)
 {
-    const uint32_t known = RQA_SEL_LEARNED | RQA_FULL_HIST | RQA_SEL_SAMPLE | RQA_SEL_WINDOW;
+    const uint32_t known = RQA_SEL_LEARNED | RQA_FULL_HIST | RQA_SEL_SAMPLE | RQA_SEL_WINDOW | RQA_SEL_PLAIN;
     if (flags & ~known) return fail(RQA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
-    if (flags & RQA_FULL_HIST) return fail(RQA_ERR_UNSUPPORTED, "RQA_FULL_HIST is a flag of rqa_det_curve only");
-    const uint32_t m = flags & (RQA_SEL_LEARNED | RQA_SEL_SAMPLE | RQA_SEL_WINDOW);
+    if (flags & RQA_FULL_HIST)
+        return fail(RQA_ERR_UNSUPPORTED, "RQA_FULL_HIST is a flag of rqa_det_curve (rqa_batch_hist gives the "
+                                         "histogram with the whole path)");
+    const uint32_t m = flags & (RQA_SEL_LEARNED | RQA_SEL_SAMPLE | RQA_SEL_WINDOW | RQA_SEL_PLAIN);
     if (m & (m - 1)) return fail(RQA_ERR_INVALID_ARG, "choose one selection method");
-    *sel = (m == RQA_SEL_LEARNED) ? 1 : (m == RQA_SEL_SAMPLE) ? 2 : (m == RQA_SEL_WINDOW) ? 3 : 0;
+    *sel = (m == RQA_SEL_LEARNED) ? 1 : (m == RQA_SEL_SAMPLE) ? 2 : (m == RQA_SEL_WINDOW) ? 3
+         : (m == RQA_SEL_PLAIN) ? 0 : -1;
     return RQA_OK;
+}
+
+// RQA_SEL_AUTO: the sample window (two passes over the pairs, exact, plain
+// fallback) for calls of at least AUTO_WINDOW_PAIRS pairs in all, else the
+// plain radix passes.  Measured on MI355X at K = 20 (ms per call, plain /
+// sample window): two N = 1e5 series 9.2 / 7.3, the 600-series ensemble
+// 12.4 / 11.3, 15 series of N = 1e4 in one call 1.54 / 1.49, ten of N = 1e3
+// 0.33 / 0.44, one N = 1e4 series 0.43 / 0.49 (the sketch and window set-up
+// cost about 0.1 ms per call).
+constexpr uint64_t AUTO_WINDOW_PAIRS = 1ull << 29;
+
+int resolve_method(const Job& job, int sel)
+{
+    if (sel >= 0) return sel;
+    uint64_t pairs = 0;
+    for (const Series& z : job.series) {
+        const uint64_t a = z.n - (uint64_t)(z.p.m - 1) * z.p.tau - z.p.theiler;
+        pairs += a * (a + 1) / 2;
+    }
+    return pairs >= AUTO_WINDOW_PAIRS ? 2 : 0;
 }
 
 rqa_status single_job_setup(rqa_ctx* c, Job& job, const float* series, uint64_t n, const rqa_params* p,
@@ -1124,6 +1168,51 @@ rqa_status tune_job(rqa_ctx* c, Job& job, uint32_t* seg_out, uint32_t* chunk_out
     return RQA_OK;
 }
 
+// Full line-length histogram P_r(l) (lengths 0 .. hist_len-1) of every
+// series of `src` at the thresholds eps_bits[S*K] (caller order), written to
+// hist_out[S][K][hist_len].  One histogram pass takes at most
+// HIST_MAX_K_HOST thresholds (its ranks and per-lane stacks are sized for
+// them), so larger K runs in ceil(K / HIST_MAX_K_HOST) passes of balanced
+// slices of the targets, inside this one call.
+rqa_status hist_in_passes(rqa_ctx* c, const Job& src, const std::vector<uint32_t>& eps_bits, uint32_t hist_len,
+                          uint64_t* hist_out)
+{
+    const uint32_t S = (uint32_t)src.series.size(), K = src.K;
+    for (uint32_t s = 0; s < S; ++s) {
+        const Series& z = src.series[s];
+        const uint64_t nv = z.n - (uint64_t)(z.p.m - 1) * z.p.tau;
+        if (nv >= (1ull << 24) - 1)
+            return fail(RQA_ERR_UNSUPPORTED, "series %u has %llu embedded vectors; the full histogram takes fewer than "
+                        "2^24 - 1", s, (unsigned long long)nv);
+    }
+    const uint32_t passes = (K + HIST_MAX_K_HOST - 1) / HIST_MAX_K_HOST;
+    const uint32_t per = (K + passes - 1) / passes;
+    for (uint32_t r0 = 0; r0 < K; r0 += per) {
+        const uint32_t kc = std::min(per, K - r0);
+        Job hj;
+        hj.series = src.series;
+        hj.base = src.base;
+        hj.K = kc;
+        hj.mode = MODE_HIST;
+        hj.hist_len = hist_len;
+        hj.eps_bits.resize((size_t)S * kc);
+        uint32_t kp = 1;
+        for (uint32_t s = 0; s < S; ++s) {
+            std::vector<uint32_t> d(eps_bits.begin() + (size_t)s * K + r0, eps_bits.begin() + (size_t)s * K + r0 + kc);
+            std::copy(d.begin(), d.end(), hj.eps_bits.begin() + (size_t)s * kc);
+            std::sort(d.begin(), d.end());
+            kp = std::max(kp, (uint32_t)(std::unique(d.begin(), d.end()) - d.begin()));
+        }
+        hj.hist_kp = kp;
+        // this slice's rows go straight to their place in the caller's rows
+        hj.hist_dst = hist_out + (size_t)r0 * hist_len;
+        hj.hist_series_stride = (size_t)K * hist_len;
+        rqa_status st = run_job(c, hj);
+        if (st) return st;
+    }
+    return RQA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1269,9 +1358,9 @@ rqa_status rqa_select_thresholds(rqa_ctx* c, const float* series, uint64_t n, co
     if (!eps_out) return fail(RQA_ERR_INVALID_ARG, "eps_out is NULL");
     Job job;
     if ((st = single_job_setup(c, job, series, n, p, rr, K))) return st;
-    job.sel = sel;
+    job.sel = resolve_method(job, sel);
     job.mode = MODE_SELECT;
-    if (sel) {
+    if (job.sel) {
         if ((st = select_windowed(c, job))) return st;
     } else {
         c->stat_passes = 3;
@@ -1303,30 +1392,7 @@ rqa_status rqa_det_curve(rqa_ctx* c, const float* series, uint64_t n, const rqa_
     Job job;
     rqa_status st = single_job(c, job, series, n, p, nullptr, eps, K, MODE_SWEEP);
     if (st) return st;
-    if (full) {
-        // distinct thresholds (the kernel packs ranks into 8 bits and keeps one
-        // stack entry per rank) and positions below 2^24 - 1
-        std::vector<uint32_t> d(job.eps_bits);
-        std::sort(d.begin(), d.end());
-        const uint32_t kp = (uint32_t)(std::unique(d.begin(), d.end()) - d.begin());
-        if (kp > HIST_MAX_K_HOST)
-            return fail(RQA_ERR_UNSUPPORTED, "%u distinct thresholds; the full histogram takes at most %u", kp,
-                        (unsigned)HIST_MAX_K_HOST);
-        const uint64_t nv = n - (uint64_t)(p->m - 1) * p->tau;
-        if (nv >= (1ull << 24) - 1)
-            return fail(RQA_ERR_UNSUPPORTED, "%llu embedded vectors; the full histogram takes fewer than 2^24 - 1",
-                        (unsigned long long)nv);
-        Job hj;
-        hj.series = job.series;
-        hj.base = job.base;
-        hj.K = K;
-        hj.mode = MODE_HIST;
-        hj.eps_bits = job.eps_bits;
-        hj.hist_len = (uint32_t)hist_len;
-        hj.hist_kp = kp;
-        hj.hist_dst = hist_out;
-        if ((st = run_job(c, hj))) return st;
-    }
+    if (full && (st = hist_in_passes(c, job, job.eps_bits, (uint32_t)hist_len, hist_out))) return st;
     for (uint32_t r = 0; r < K; ++r) {
         count_out[r] = job.count[r];
         rr_out[r] = job.rr[r];
@@ -1347,7 +1413,7 @@ rqa_status rqa_run(rqa_ctx* c, const float* series, uint64_t n, const rqa_params
     if (!det_mean_out) return fail(RQA_ERR_INVALID_ARG, "det_mean_out is NULL");
     Job job;
     if ((st = single_job_setup(c, job, series, n, p, rr, K))) return st;
-    job.sel = sel;
+    job.sel = resolve_method(job, sel);
     if ((st = select_and_sweep(c, job))) return st;
     for (uint32_t r = 0; r < K; ++r) {
         if (eps_out) eps_out[r] = job.eps[r];
@@ -1372,7 +1438,7 @@ rqa_status rqa_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t
     if (!eps_out || !rr_out || !det_out || !det_mean_out) return fail(RQA_ERR_INVALID_ARG, "an output is NULL");
     Job job;
     if ((st = build_batch_job(job, S, concat, offsets, p, rr, K))) return st;
-    job.sel = sel;
+    job.sel = resolve_method(job, sel);
     if ((st = select_and_sweep(c, job))) return st;
     for (size_t i = 0; i < (size_t)S * K; ++i) {
         eps_out[i] = job.eps[i];
@@ -1394,12 +1460,46 @@ rqa_status rqa_batch_static(rqa_ctx* c, uint32_t S, const float* concat, const u
     int sel = 0;
     if ((st = check_flags_select(flags, &sel))) return st;
     // the network's activations live in allocated memory
-    if (sel == 1) return fail(RQA_ERR_UNSUPPORTED, "rqa_batch_static takes RQA_SEL_PLAIN, RQA_SEL_SAMPLE or RQA_SEL_WINDOW");
+    if (sel == 1)
+        return fail(RQA_ERR_UNSUPPORTED, "rqa_batch_static takes RQA_SEL_AUTO, RQA_SEL_PLAIN, RQA_SEL_SAMPLE or "
+                                         "RQA_SEL_WINDOW");
     if (!c->static_dev) return fail(RQA_ERR_DEVICE, "the static scratch of device %d is not resolved", c->device);
     c->use_static = true;
     st = rqa_batch(c, S, concat, offsets, p, rr, K, flags, eps_out, rr_out, det_out, det_mean_out, count_out);
     c->use_static = false;
     return st;
+}
+
+rqa_status rqa_batch_hist(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets, const rqa_params* p,
+                          const double* rr, uint32_t K, uint32_t flags, float* eps_out, double* rr_out,
+                          double* det_out, double* det_mean_out, uint64_t* count_out, uint64_t* hist_out,
+                          uint64_t hist_len)
+{
+    if (c) reset_phases(c);
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    int sel = 0;
+    if ((st = check_flags_select(flags, &sel))) return st;
+    if (!eps_out || !rr_out || !det_out || !det_mean_out || !hist_out)
+        return fail(RQA_ERR_INVALID_ARG, "an output is NULL");
+    if (hist_len < 1 || hist_len > RQA_MAX_HIST_LEN)
+        return fail(RQA_ERR_INVALID_ARG, "hist_len=%llu outside 1..%u", (unsigned long long)hist_len,
+                    (unsigned)RQA_MAX_HIST_LEN);
+    Job job;
+    if ((st = build_batch_job(job, S, concat, offsets, p, rr, K))) return st;
+    job.sel = resolve_method(job, sel);
+    if ((st = select_and_sweep(c, job))) return st;
+    std::vector<uint32_t> bits((size_t)S * K);
+    std::memcpy(bits.data(), job.eps.data(), sizeof(uint32_t) * bits.size());
+    if ((st = hist_in_passes(c, job, bits, (uint32_t)hist_len, hist_out))) return st;
+    for (size_t i = 0; i < (size_t)S * K; ++i) {
+        eps_out[i] = job.eps[i];
+        rr_out[i] = job.rr[i];
+        det_out[i] = job.det[i];
+        if (count_out) count_out[i] = job.count[i];
+    }
+    for (uint32_t s = 0; s < S; ++s) det_mean_out[s] = job.det_mean[s];
+    return RQA_OK;
 }
 
 rqa_status rqa_autotune(rqa_ctx* c, const float* series, uint64_t n, const rqa_params* p, const double* rr, uint32_t K,

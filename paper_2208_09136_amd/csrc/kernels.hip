@@ -2229,7 +2229,10 @@ __device__ void set_window(SeriesWork& w, int64_t lo, int64_t hi, bool valid)
     w.win_lo = (uint32_t)lo;
     w.win_span = span;
     w.win_shift = sh;
-    w.win_ok = sh <= WIN_MAX_SHIFT ? 1u : 0u;
+    // window pass 1 counts keys below the window in the fine bin below its
+    // start, so the start must be at least one fine bin above key 0 (keys
+    // that small are denormals or zeros; such series take the plain passes)
+    w.win_ok = (sh <= WIN_MAX_SHIFT && (uint64_t)lo >= (1ull << sh)) ? 1u : 0u;
 }
 
 // Window from predicted offsets t_r (network output) and half-widths d_r:
@@ -2305,43 +2308,40 @@ hipError_t launch_window_from_sample(hipStream_t st, const DevBufs& b, const uin
 // WIN_BINS fine bins.
 template <int NORM, int MC, int TC>
 struct WinPass1 {
-    uint32_t* bins;       // LDS [WIN_BINS]
+    uint32_t* bins;       // LDS [1 + WIN_BINS]: [0] keys below the window, [1 + f] fine bin f
     uint64_t* gbins;      // global [S][WIN_BINS]
     SeriesWork* works;
-    uint32_t lo, span, shift;
-    uint32_t below = 0;   // per lane
+    uint32_t base;        // win_lo - 2^shift: the key one fine bin below the window start
+    uint32_t hi, shift;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
-        lo = uniform(w.win_lo);
-        span = uniform(w.win_span);
+        const uint32_t lo = uniform(w.win_lo);
         shift = uniform(w.win_shift);
+        hi = lo + uniform(w.win_span);
+        base = lo - (1u << shift);  // the window set-up keeps win_lo >= 2^shift
         active = uniform(w.win_ok) != 0;
-        below = 0;
-        for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) bins[i] = 0u;
+        for (uint32_t i = threadIdx.x; i <= WIN_BINS; i += blockDim.x) bins[i] = 0u;
     }
     __device__ void flush(uint32_t s)
     {
         if (!active) return;
         for (uint32_t i = threadIdx.x; i < WIN_BINS; i += blockDim.x) {
-            const uint32_t v = bins[i];
+            const uint32_t v = bins[1 + i];
             if (v) atomicAdd((unsigned long long*)&gbins[(size_t)s * WIN_BINS + i], (unsigned long long)v);
         }
-        // one atomic per wave on the series' single counter (not one per lane)
-        uint32_t b = below;
-        for (int off = 32; off > 0; off >>= 1) b += __shfl_xor(b, off);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)b);
-        below = 0;
+        if (threadIdx.x == 0 && bins[0]) atomicAdd((unsigned long long*)&works[s].win_below, (unsigned long long)bins[0]);
     }
     __device__ __forceinline__ uint32_t look(uint32_t) const { return 0u; }
+    // Keys at most the window end count in LDS bin (key - base) >> shift,
+    // saturated at 0: every key below the window start lands in bin 0 and a
+    // window key v in bin ((v - win_lo) >> shift) + 1.  A branch: most keys
+    // lie above the window, and an atomic per key would cost more than the
+    // divergence.
     __device__ __forceinline__ void count(uint32_t u, uint32_t)
     {
-        const uint32_t rel = u - lo;
-        below += u < lo ? 1u : 0u;
-        // a branch: most keys lie outside the window, and an atomic per key
-        // would cost more than the divergence
-        if (rel <= span) atomicAdd(&bins[rel >> shift], 1u);
+        if (u <= hi) atomicAdd(&bins[__builtin_elementwise_sub_sat(u, base) >> shift], 1u);
     }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
@@ -2390,7 +2390,7 @@ struct WinPass2 {
     }
 };
 
-__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass) { return (pass == 1 ? WIN_BINS * 4 : WIN_BINS) + 16; }
+__host__ __device__ __forceinline__ size_t window_lds_bytes_dev(int pass) { return (pass == 1 ? (WIN_BINS + 1) * 4 : WIN_BINS) + 16; }
 
 size_t window_lds_bytes(int pass) { return window_lds_bytes_dev(pass); }
 

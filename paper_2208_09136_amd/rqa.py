@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "librqa.so")
 RQA_MAX_K = 128
 RQA_NORM_MAX = 0
 RQA_NORM_EUCLIDEAN = 1
-RQA_SEL_PLAIN = 0
+RQA_SEL_AUTO = 0
+RQA_SEL_PLAIN = 16
 RQA_SEL_LEARNED = 1
 RQA_FULL_HIST = 2
 RQA_SEL_SAMPLE = 4
@@ -57,6 +58,7 @@ SIGNATURES = {
     "rqa_run": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, _u32, _fp, _up, _up, _dp, _dp, _dp]),
     "rqa_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up]),
     "rqa_batch_static": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up]),
+    "rqa_batch_hist": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, _u32, _fp, _dp, _dp, _dp, _up, _up, _u64]),
     "rqa_phase_times": (_i32, [_vp, _dp, _i32]),
     "rqa_set_timing": (_i32, [_vp, _i32]),
     "rqa_valu_rate": (_i32, [_vp, _u32, _dp, _dp]),
@@ -328,7 +330,7 @@ def rqa_tune_load(ctx, path):
     _check(load().rqa_tune_load(ctx, os.fsencode(path)))
 
 
-def rqa_select_thresholds(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
+def rqa_select_thresholds(ctx, series, params, rr, flags=RQA_SEL_AUTO):
     """Exact thresholds for the RR targets: (eps float32[K], k uint64[K],
     count uint64[K])."""
     ptr, n = _series_ptr(series)
@@ -367,7 +369,7 @@ def rqa_det_curve(ctx, series, params, eps, flags=0, hist_len=0):
     return {"count": cnt, "rr": rr, "det": det, "det_mean": float(dm[0]), "hist": hist}
 
 
-def rqa_run(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
+def rqa_run(ctx, series, params, rr, flags=RQA_SEL_AUTO):
     """Thresholds for the targets, then RR/DET at them: dict(eps, k, count,
     rr, det, det_mean)."""
     ptr, n = _series_ptr(series)
@@ -386,7 +388,7 @@ def rqa_run(ctx, series, params, rr, flags=RQA_SEL_PLAIN):
     return {"eps": eps, "k": k, "count": cnt, "rr": rro, "det": det, "det_mean": float(dm[0])}
 
 
-def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN, _entry="rqa_batch"):
+def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_AUTO, _entry="rqa_batch"):
     """S series back to back in one device tensor.  offsets: S+1 element
     offsets; params: S parameter sets; rr: (S, K) targets.  Returns dict of
     (S, K) arrays eps, rr, det, count and det_mean (S,)."""
@@ -413,7 +415,31 @@ def rqa_batch(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN, _entry="rqa
 RQA_STATIC_SCRATCH_BYTES = 64 << 20
 
 
-def rqa_batch_static(ctx, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+def rqa_batch_hist(ctx, concat, offsets, params, rr, hist_len, flags=RQA_SEL_AUTO):
+    """rqa_batch plus the full line-length histogram at every selected
+    threshold: the dict also holds "hist", an (S, K, hist_len) uint64 array."""
+    ptr, _ = _series_ptr(concat)
+    offs = _a(offsets, np.uint64)
+    S = len(offs) - 1
+    rrt = _a(rr, np.float64)
+    if rrt.ndim != 2 or rrt.shape[0] != S:
+        raise ValueError("rr must have shape (S, K)")
+    K = rrt.shape[1]
+    prm = (rqa_params * S)(*[_params(p) for p in params])
+    eps = np.zeros((S, K), np.float32)
+    rro = np.zeros((S, K), np.float64)
+    det = np.zeros((S, K), np.float64)
+    cnt = np.zeros((S, K), np.uint64)
+    dm = np.zeros(S, np.float64)
+    hist = np.zeros((S, K, int(hist_len)), np.uint64)
+    _check(load().rqa_batch_hist(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, _p(rrt, ctypes.c_double), K, flags,
+                                 _p(eps, ctypes.c_float), _p(rro, ctypes.c_double), _p(det, ctypes.c_double),
+                                 _p(dm, ctypes.c_double), _p(cnt, ctypes.c_uint64), _p(hist, ctypes.c_uint64),
+                                 int(hist_len)))
+    return {"eps": eps, "rr": rro, "det": det, "det_mean": dm, "count": cnt, "hist": hist}
+
+
+def rqa_batch_static(ctx, concat, offsets, params, rr, flags=RQA_SEL_AUTO):
     """rqa_batch with device scratch from the library's static area: the call
     allocates no device memory (see include/rqa.h)."""
     return rqa_batch(ctx, concat, offsets, params, rr, flags, _entry="rqa_batch_static")
@@ -442,20 +468,23 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    def select_thresholds(self, series, params, rr, flags=RQA_SEL_PLAIN):
+    def select_thresholds(self, series, params, rr, flags=RQA_SEL_AUTO):
         return rqa_select_thresholds(self.ctx, series, params, rr, flags)
 
     def det_curve(self, series, params, eps, flags=0, hist_len=0):
         return rqa_det_curve(self.ctx, series, params, eps, flags, hist_len)
 
-    def run(self, series, params, rr, flags=RQA_SEL_PLAIN):
+    def run(self, series, params, rr, flags=RQA_SEL_AUTO):
         return rqa_run(self.ctx, series, params, rr, flags)
 
-    def batch(self, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+    def batch(self, concat, offsets, params, rr, flags=RQA_SEL_AUTO):
         return rqa_batch(self.ctx, concat, offsets, params, rr, flags)
 
-    def batch_static(self, concat, offsets, params, rr, flags=RQA_SEL_PLAIN):
+    def batch_static(self, concat, offsets, params, rr, flags=RQA_SEL_AUTO):
         return rqa_batch_static(self.ctx, concat, offsets, params, rr, flags)
+
+    def batch_hist(self, concat, offsets, params, rr, hist_len, flags=RQA_SEL_AUTO):
+        return rqa_batch_hist(self.ctx, concat, offsets, params, rr, hist_len, flags)
 
     def set_timing(self, enable=True):
         rqa_set_timing(self.ctx, enable)

@@ -147,10 +147,12 @@ def test_histogram_limits(ctx):
     p = (1, 1, 0, 1, 2)
     e33 = eps_set(c["y"], 1, 1, 0, 1, np.linspace(0.01, 0.5, 33))
     assert len(np.unique(e33)) == 33
-    with pytest.raises(RqaError) as e:
-        ctx.det_curve(y, p, e33, hist_len=10)
-    assert e.value.name == "RQA_ERR_UNSUPPORTED"
-    # 33 thresholds with 32 distinct values are accepted
+    # 33 distinct thresholds: one more than a histogram pass takes, so two
+    # passes in the call
+    got = ctx.det_curve(y, p, e33, hist_len=10)
+    want = oracle.lines(c["y"], 1, 1, 0, 1, 2, e33, hist_len=10)
+    assert np.array_equal(got["hist"], want["hist"])
+    # 33 thresholds with 32 distinct values
     e = np.concatenate([e33[:32], e33[:1]])
     got = ctx.det_curve(y, p, e, hist_len=10)
     want = oracle.lines(c["y"], 1, 1, 0, 1, 2, e, hist_len=10)
@@ -185,3 +187,90 @@ def test_full_size_identities(ctx):
     D = (h[:, c["lmin"]:] * l[c["lmin"]:]).sum(axis=1)
     assert np.array_equal(D, np.round(got["det"] * got["count"].astype(np.float64)).astype(np.int64))
     assert (h[:, 0] == 0).all() and (h >= 0).all()
+
+
+@pytest.mark.parametrize("name", ["sine_m1_euclid", "lorenz_m3t5_w5_dups"])
+def test_paper_rr_set_in_one_call(ctx, name):
+    """The paper's RR set 1..99 % (four histogram passes in one call), every
+    row element by element against the oracle, unlumped and lumped."""
+    c = next(x for x in CASES if x["name"] == name)
+    p = (c["m"], c["tau"], c["norm"], c["w"], c["lmin"])
+    nv = nv_of(len(c["y"]), c["m"], c["tau"])
+    eps = eps_set(c["y"], c["m"], c["tau"], c["norm"], c["w"], np.arange(1, 100) / 100.0)
+    assert len(np.unique(eps)) > 90
+    y = dev(c["y"])
+    for hl in (nv + 1, 7):
+        print(f"[hist] {name} K=99 hist_len={hl}", flush=True)
+        got = ctx.det_curve(y, p, eps, hist_len=hl)
+        want = oracle.lines(c["y"], c["m"], c["tau"], c["norm"], c["w"], c["lmin"], eps, hist_len=hl)
+        assert np.array_equal(got["hist"], want["hist"]), hl
+        assert np.array_equal(got["count"], want["count"])
+
+
+def batch_of(cases_):
+    import torch
+    offs = np.concatenate([[0], np.cumsum([len(c["y"]) for c in cases_])]).astype(np.uint64)
+    concat = torch.from_numpy(np.concatenate([c["y"] for c in cases_])).to("cuda:0")
+    prm = [(c["m"], c["tau"], c["norm"], c["theiler"], c["lmin"]) for c in cases_]
+    return concat, offs, prm
+
+
+@pytest.mark.parametrize("K", [20, 99])
+def test_batch_hist_equals_oracle(ctx, K):
+    """The whole path plus the histogram at the selected thresholds in one
+    call, for a slice of the ensemble (both embedding groups): thresholds,
+    counts, DET and every histogram entry against the oracle's run."""
+    import concurrent.futures as cf
+    ens = synth.config_batch(realisations=1)
+    short = [c for c in ens if len(c["y"]) <= 3000]
+    sel = [c for c in short if c["m"] == 1][::3] + [c for c in short if c["m"] == 3][::2]
+    assert {c["m"] for c in sel} == {1, 3} and len(sel) >= 8
+    rr = np.tile(np.arange(1, K + 1) / 100.0, (len(sel), 1))
+    concat, offs, prm = batch_of(sel)
+    hl = max(len(c["y"]) for c in sel) + 1
+    print(f"[hist] batch_hist {len(sel)} series K={K} hist_len={hl}", flush=True)
+    got = ctx.batch_hist(concat, offs, prm, rr, hl)
+    plain = ctx.batch(concat, offs, prm, rr)
+    for key in ("eps", "count", "det", "det_mean"):
+        assert np.array_equal(got[key], plain[key], equal_nan=True), key
+
+    def want(i):
+        c = sel[i]
+        return oracle.run(c["y"], c["m"], c["tau"], c["norm"], c["theiler"], c["lmin"], rr[i], hist_len=hl)
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        wants = list(ex.map(want, range(len(sel))))
+    for i, w in enumerate(wants):
+        assert np.array_equal(got["eps"][i].view(np.uint32), w["eps"].view(np.uint32)), i
+        assert np.array_equal(got["count"][i], w["count"]), i
+        assert np.array_equal(got["hist"][i], w["hist"]), i
+
+
+def test_batch_hist_full_size_k99(ctx):
+    """Both N = 10^5 bench series at the paper's 99 targets in one call: the
+    averaged L and L_max curves come from its rows.  Every row satisfies
+    sum_l l P(l) = C and sum_{l >= lmin} l P(l) = D; three rows per series,
+    one from each of three histogram passes, equal the oracle's element by
+    element."""
+    from paper_2208_09136_amd import rqa
+    cases_ = synth.config_large()
+    concat, offs, prm = batch_of(cases_)
+    rr = np.tile(np.arange(1, 100) / 100.0, (2, 1))
+    nv = nv_of(100_000, 3, 5)
+    print("[hist] batch_hist 2 x N=1e5 K=99", flush=True)
+    got = ctx.batch_hist(concat, offs, prm, rr, nv + 1)
+    ref = ctx.batch(concat, offs, prm, rr)
+    for key in ("eps", "count", "det"):
+        assert np.array_equal(got[key], ref[key]), key
+    l = np.arange(nv + 1, dtype=np.int64)
+    for s, c in enumerate(cases_):
+        h = got["hist"][s].astype(np.int64)
+        assert np.array_equal((h * l).sum(axis=1).astype(np.uint64), got["count"][s])
+        D = (h[:, 2:] * l[2:]).sum(axis=1)
+        assert np.array_equal(D, np.round(got["det"][s] * got["count"][s].astype(np.float64)).astype(np.int64))
+        L, lmax = rqa.rqa_line_measures(got["hist"][s], 2)
+        assert np.isfinite(rqa.rqa_averaged_det(L)).all() and (lmax >= 2).all()
+        rows = [4, 50, 97]
+        print(f"[hist] {c['name']} oracle rows {rows}", flush=True)
+        want = oracle.lines(c["y"], 3, 5, 1, 1, 2, got["eps"][s][rows], hist_len=nv + 1)
+        assert np.array_equal(got["hist"][s][rows], want["hist"])

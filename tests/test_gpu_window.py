@@ -141,3 +141,24 @@ def test_nonfinite_series_rejected_in_every_selection_mode(ctx):
     # the context still works afterwards
     got = ctx.run(dev(c["y"]), prm(c), c["rr"], flags=SAMPLE)
     assert np.array_equal(got["eps"], ctx.run(dev(c["y"]), prm(c), c["rr"])["eps"])
+
+
+def test_automatic_method_by_call_size(ctx):
+    """RQA_SEL_AUTO (flags 0) takes the plain radix passes for small calls and
+    the sample window from 2^29 pairs on; the results equal the plain
+    method's either way."""
+    from paper_2208_09136_amd import rqa
+    small = CASES[1]
+    ctx.run(dev(small["y"]), prm(small), small["rr"])
+    assert ctx.selection_stats()["full_passes"] == 3
+    # N = 32,800, m = 1: 537,903,600 pairs >= 2^29
+    y = synth.series("logistic", 32_800, 0.0, (8, 9, 9, 9))
+    p = (1, 1, 1, 1, 2)
+    print("[window] automatic method, N = 32800", flush=True)
+    auto = ctx.run(dev(y), p, synth.RR_20)
+    st = ctx.selection_stats()
+    assert st["full_passes"] in (2, 5)
+    plain = ctx.run(dev(y), p, synth.RR_20, flags=rqa.RQA_SEL_PLAIN)
+    assert ctx.selection_stats()["full_passes"] == 3
+    for key in ("eps", "k", "count", "det"):
+        assert np.array_equal(auto[key], plain[key]), key
