@@ -2,18 +2,20 @@
 """Benchmark of the averaged-RQA hot path on one MI355X.
 
 A step is one whole pass of the path over the large workload: exact
-threshold selection for K = 20 target recurrence rates (two radix counting
-passes, the last bits resolved by the line sweep) and the line sweep giving
-RR, DET and the averaged DET, for both large series (Lorenz-x + 0 dB noise
-and logistic r=4 + -10 dB noise, N = 10^5, m = 3, tau = 5, Euclidean norm,
-Theiler window 1, l_min = 2), as one rqa_batch call with plain selection.
-Inputs are resident in device memory before the timed region.
+threshold selection for K = 20 target recurrence rates and the line sweep
+giving RR, DET and the averaged DET, for both large series (Lorenz-x + 0 dB
+noise and logistic r=4 + -10 dB noise, N = 10^5, m = 3, tau = 5, Euclidean
+norm, Theiler window 1, l_min = 2), as one rqa_batch call with the library's
+default selection (at this size the sample window: one counting pass over
+the pairs inside a key window, the last bits resolved by the line sweep, a
+plain radix fallback for any target outside the window).  Inputs are
+resident in device memory before the timed region.
 
 value = pairs x thresholds per second over the timed steps, where pairs are
 the M = (Nv-1) Nv / 2 upper-triangle pairs each series has.
 
-Also reported (outside the timed steps): the same step with the sketch
-window and the trained network's window, the 600-series batched ensemble
+Also reported (outside the timed steps): the same step with plain radix
+selection and with the trained network's window, the 600-series batched ensemble
 (series/s, batched against one call per series), the network on 200
 held-out series, per-phase device times from HIP events on the library's
 stream, the roofline of the dominant kernel (with counter-derived traffic
@@ -37,13 +39,76 @@ import synth  # noqa: E402
 
 METRIC = "recurrence cells x thresholds/s at N=1e5, K=20 (+ batched series/s), % VALU peak"
 K = 20
-# VALU peak of MI355X in lane-ops/s: the FP32 vector peak of 157.3 TFLOP/s
-# counts an FMA as two, i.e. 256 CUs x 128 lanes x 2.4 GHz one-op lane slots.
+# VALU peak of MI355X in lane-ops/s from its unit counts and clock: the FP32
+# vector peak of 157.3 TFLOP/s counts an FMA as two flops, i.e. 256 CUs x 128
+# one-op lane slots per clock x 2.4 GHz.  The library's issue-rate probe
+# measures what the chip sustains (rqa_valu_rate) and is reported beside it.
 VALU_PEAK = 157.3e12 / 2
-# Algorithmic VALU lane-ops of one key for (norm, m): the m subtractions, the
-# m |.| or squares and the m-1 max or add steps.
-def key_ops(norm, m):
-    return 3 * m - 1
+# Survey count of the method's work: about 2 + key/K VALU ops per pair and
+# threshold (a compare and a run update per threshold, the key shared) --
+# 48 per pair at K = 20 with the Euclidean m = 3 key (8 ops).  The range
+# sweep does O(1) work per pair whatever K is, so this count over time is a
+# ratio to peak, not a fraction of it.
+SURVEY_OPS_PER_PAIR = 2 * K + 8
+# Lower bound of this algorithm's VALU work per pair (lane-ops), per kernel,
+# Euclidean m = 3: the key needs one new difference, its square and m - 1 = 2
+# adds per cell (the walker reuses each difference m times), 4 ops; then
+#   counting pass 1: the bucket index                                   +1
+#   counting pass 2: bucket index, slot test, sub-bucket index          +3
+#   window pass 1:   offset from the window start, range test, bin      +3
+#   range sweep:     rank (bucket index, boundary compare, add),
+#                    line rank (min, max), histogram address            +6
+# The LDS read or atomic each kernel needs per pair is not VALU work.
+KEY_OPS = 4
+LOWER_BOUND_OPS = {"select_pass1": KEY_OPS + 1, "select_pass2": KEY_OPS + 3, "window_pass1": KEY_OPS + 3,
+                   "sweep": KEY_OPS + 6}
+
+
+def valu_roofline(ph, pairs, step_sec, probe, windowed):
+    """Roofline of the dominant kernel and VALU fractions of the step.
+
+    ph: phase -> device ms per step (HIP events on the library stream; one
+    launch per phase); pairs: pairs per launch; probe: measured issue rates
+    (lane-ops/s) of a double-rate (v_add_u32) and a half-rate (v_max_u32)
+    instruction.  `achieved` counts the algorithm's lower-bound VALU work
+    (LOWER_BOUND_OPS) per launch over the launch time; measured instruction
+    counts (SQ_INSTS_VALU x 64) come from the stored counter profile while
+    it matches the device sources."""
+    names = {"select_pass1": "window_pass1" if windowed else "select_pass1", "select_pass2": "select_pass2",
+             "sweep": "sweep"}
+    phases = [p for p in ("select_pass1", "select_pass2", "sweep") if ph.get(p, 0.0) > 0.0]
+    alg = {p: pairs * LOWER_BOUND_OPS[names[p]] for p in phases}
+    dom = max(phases, key=lambda p: ph[p])
+    t = ph[dom] * 1e-3
+    achieved = alg[dom] / t
+    roof = {"bound": "alu", "kernel": names[dom], "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+            "algorithmic_ops_per_pair": LOWER_BOUND_OPS[names[dom]], "pairs_per_launch": pairs,
+            "launch_ms": ph[dom], "measured_peak": probe["v_add_u32"] / 1e12,
+            "measured_peak_half_rate": probe["v_max_u32"] / 1e12,
+            "survey_count_ratio": pairs * SURVEY_OPS_PER_PAIR / t / VALU_PEAK if names[dom] == "sweep" else None}
+    step = {"algorithmic": sum(alg.values()) / step_sec / VALU_PEAK,
+            "per_phase_algorithmic": {names[p]: alg[p] / (ph[p] * 1e-3) / VALU_PEAK for p in phases},
+            "issue": None, "per_phase_issue": None}
+    counters = stored_counters(windowed)
+    if counters:
+        kcs = counters.get("kernels", {})
+        kc = kcs.get(names[dom])
+        if kc and kc.get("fetch_bytes") is not None and kc.get("write_bytes") is not None:
+            # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, each scaled by
+            # the factor a plain copy of known size gave for that counter
+            roof["traffic"] = kc["fetch_bytes"] + kc["write_bytes"]
+            roof["traffic_unit"] = "bytes/launch"
+        if all(kcs.get(names[p], {}).get("valu_insts") is not None for p in phases):
+            # executed VALU instructions x 64 lanes over the live launch time,
+            # against the measured double-rate issue peak
+            vi = {p: kcs[names[p]]["valu_insts"] for p in phases}
+            issue = {p: vi[p] * 64 / (ph[p] * 1e-3) / probe["v_add_u32"] for p in phases}
+            step["per_phase_issue"] = {names[p]: v for p, v in issue.items()}
+            step["issue"] = sum(vi[p] * 64 for p in phases) / step_sec / probe["v_add_u32"]
+            roof["issue_frac"] = issue[dom]
+            roof["valu_insts_per_pair"] = vi[dom] * 64 / pairs
+    return roof, step
 
 
 def cells_of(case):
@@ -59,12 +124,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true", help="skip the 600-series ensemble")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=15_000,
-                    help="prefix length of the Lorenz series the oracle is timed on")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of the CPU oracle on the 600-series ensemble (series started within it)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="time the CPU oracle on the configurations only (no GPU) and print it")
     ap.add_argument("--tune-file", default=None,
                     help="load launch shapes from this file if it exists, else tune and save them there")
     ap.add_argument("--no-bracket", action="store_true", help="skip the learned-bracket evaluation")
     ap.add_argument("--no-hist", action="store_true", help="skip the full line-length histogram")
+    ap.add_argument("--select", choices=("auto", "plain", "sample"), default="auto",
+                    help="selection method of the timed step (auto: the library's default)")
     ap.add_argument("--no-extras", action="store_true",
                     help="time the plain step only (no windowed selection, K = 99 or histogram lines)")
     ap.add_argument("--bracket-file", default=os.path.join(ROOT, "paper_2208_09136_amd", "bracket_params.npz"),
@@ -88,14 +157,14 @@ def sources_digest():
     return h.hexdigest()
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "counters_n1e5_k20.json")
-
-
-def stored_counters():
-    """Per-launch hardware counters of the timed kernels (rocprofv3 --pmc,
-    summarised in profiles/), or None when absent or taken on other sources."""
+def stored_counters(windowed):
+    """Per-launch hardware counters of the timed kernels (rocprofv3 --pmc of
+    the step with window or plain selection, summarised in profiles/ by
+    paper_2208_09136_amd.profsum), or None when absent or taken on other
+    sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_n1e5_k20_{'window' if windowed else 'plain'}.json")
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
@@ -109,6 +178,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by diagonal "
                                    "bands across GPUs in design only", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.cpu_only:
+        print(json.dumps({"cpu_baseline": cpu_baseline(args.cpu_budget)}), flush=True)
+        return
 
     import torch
     from paper_2208_09136_amd import rqa
@@ -138,61 +211,43 @@ def main():
     t_tune = time.perf_counter() - t_tune
     ctx.set_timing(True)
 
+    # the step: the library's default selection (RQA_SEL_AUTO: the sample
+    # window at this size, exact, with the plain fallback)
+    step_flags = {"auto": rqa.RQA_SEL_AUTO, "plain": rqa.RQA_SEL_PLAIN, "sample": rqa.RQA_SEL_SAMPLE}[args.select]
     ref = None
     for _ in range(args.warmup):
-        ref = ctx.batch(concat, offs, prm, rr)
+        ref = ctx.batch(concat, offs, prm, rr, flags=step_flags)
     torch.cuda.synchronize()
     phases = np.zeros(len(rqa.PHASES))
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = ctx.batch(concat, offs, prm, rr)
+        out = ctx.batch(concat, offs, prm, rr, flags=step_flags)
         phases += np.array([ctx.phase_times()[p] for p in rqa.PHASES])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if ref is not None:
         assert np.array_equal(ref["det_mean"], out["det_mean"]), "results changed between steps"
+    step_stats = ctx.selection_stats()
+    windowed = step_stats["full_passes"] != 3
     sec = (t1 - t0) / args.steps
     value = cell_thr / sec
     ph = dict(zip(rqa.PHASES, (phases / args.steps).tolist()))
 
-    # roofline of the dominant kernel: the phase with the largest device time;
-    # one launch per phase per step.  Algorithmic lane-ops per pair: the key
-    # (3m - 1), then per counting pass 6 (bucket, table lookup, count) and for
-    # the line sweep 2 per threshold (one comparison, one run-length update)
-    # plus the 6 of the last radix pass it takes over.
-    kops = key_ops(1, 3)
-    per_launch_ops = {
-        "select_pass1": sum(cells) * (kops + 6),
-        "select_pass2": sum(cells) * (kops + 6),
-        "sweep": sum(cells) * (kops + 6 + 2 * K),
-    }
-    dom = max(per_launch_ops, key=lambda p: ph[p])
-    achieved = per_launch_ops[dom] / (ph[dom] * 1e-3)
-    step_ops = sum(per_launch_ops.values())
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                "algorithmic_ops_per_launch": per_launch_ops[dom], "launch_ms": ph[dom]}
-    counters = stored_counters()
-    if counters and dom in counters.get("kernels", {}):
-        kc = counters["kernels"][dom]
-        # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, each scaled by
-        # the factor a plain copy of known size gave for that counter
-        if kc.get("fetch_bytes") is not None and kc.get("write_bytes") is not None:
-            roofline["traffic"] = kc["fetch_bytes"] + kc["write_bytes"]
-            roofline["traffic_unit"] = "bytes/launch"
-        if kc.get("valu_insts") is not None:
-            # executed VALU instructions x 64 lanes against the same peak
-            roofline["valu_lane_ops_measured"] = kc["valu_insts"] * 64
-            roofline["valu_busy_frac"] = kc["valu_insts"] * 64 / (ph[dom] * 1e-3) / VALU_PEAK
+    # roofline of the dominant kernel (the phase with the largest device time;
+    # one launch per phase per step) and the step's fraction of VALU peak
+    probe = {k: rqa.rqa_valu_rate(ctx.ctx, k)[0] for k in ("v_add_u32", "v_max_u32")}
+    roofline, step_frac = valu_roofline(ph, sum(cells), sec, probe, windowed=windowed)
 
-    # the same step with windowed selection (sketch-sample window, and the
-    # trained network's window when present): identical results, fewer passes
-    windows = {}
+    # the same step with each selection method: identical results, different
+    # numbers of passes over the pairs (plain radix: three; sample or network
+    # window: two)
+    methods = {}
     from paper_2208_09136_amd import bracket
     have_net = not args.no_bracket and os.path.exists(args.bracket_file)
     if have_net:
         bracket.load(ctx, args.bracket_file)
-    for name, flags in (("sample", rqa.RQA_SEL_SAMPLE), ("network", rqa.RQA_SEL_LEARNED)):
+    for name, flags in (("plain", rqa.RQA_SEL_PLAIN), ("sample", rqa.RQA_SEL_SAMPLE),
+                        ("network", rqa.RQA_SEL_LEARNED)):
         if args.no_extras or (name == "network" and not have_net):
             continue
         got = ctx.batch(concat, offs, prm, rr, flags=flags)
@@ -204,11 +259,11 @@ def main():
         wsec = (time.perf_counter() - t0) / args.steps
         st = ctx.selection_stats()
         wph = ctx.phase_times()
-        windows[name] = {"ms_per_step": wsec * 1e3, "value": cell_thr / wsec, "full_passes": st["full_passes"],
+        methods[name] = {"ms_per_step": wsec * 1e3, "value": cell_thr / wsec, "full_passes": st["full_passes"],
                          "phases_ms": wph,
                          "series_fallback": st["series_fallback"],
                          "identical": bool(all(np.array_equal(got[k], out[k]) for k in ("eps", "count", "det"))),
-                         "speedup_vs_plain": sec / wsec}
+                         "step_over_this": wsec / sec}
 
     k99 = None if args.no_extras else bench_k99(ctx, torch, rqa, concat, offs, prm, len(cases), sum(cells),
                                                  args.steps)
@@ -227,9 +282,12 @@ def main():
                    "parallelism": "single-gpu"},
         "phases_ms": ph,
         "autotune": {"chunk_tiles": tuned_chunk, "seconds": t_tune},
-        "valu_peak_frac": step_ops / sec / VALU_PEAK,
+        "valu_peak_frac": step_frac["algorithmic"],
+        "valu_peak": step_frac,
         "roofline": roofline,
-        "windowed_selection": windows,
+        "selection": {"method": "sample window" if windowed else "plain radix",
+                      "full_passes": step_stats["full_passes"], "series_fallback": step_stats["series_fallback"]},
+        "selection_methods": methods,
         "k99": k99,
         "full_histogram": full_hist,
         "sorting_rate": sorting,
@@ -243,7 +301,7 @@ def main():
         result["learned_bracket"] = bench_bracket(ctx, torch, args)
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(cases[0], args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_budget)
 
     if args.copy_mib > 0:
         n = args.copy_mib << 20
@@ -269,18 +327,18 @@ def bench_k99(ctx, torch, rqa, concat, offs, prm, nseries, cells, steps):
     torch.cuda.synchronize()
     sec99 = (time.perf_counter() - t0) / steps
     ph99 = ctx.phase_times()
-    # the same with the sketch-sample window (identical results)
-    win = ctx.batch(concat, offs, prm, rr99, flags=rqa.RQA_SEL_SAMPLE)
+    # the same with plain radix selection (identical results)
+    pl = ctx.batch(concat, offs, prm, rr99, flags=rqa.RQA_SEL_PLAIN)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        win = ctx.batch(concat, offs, prm, rr99, flags=rqa.RQA_SEL_SAMPLE)
+        pl = ctx.batch(concat, offs, prm, rr99, flags=rqa.RQA_SEL_PLAIN)
     torch.cuda.synchronize()
-    secw = (time.perf_counter() - t0) / steps
+    secp = (time.perf_counter() - t0) / steps
     return {"ms_per_step": sec99 * 1e3, "value": cells * 99 / sec99, "unit": "cell-thresholds/s",
             "phases_ms": ph99,
-            "sample_window_ms_per_step": secw * 1e3,
-            "sample_window_identical": bool(all(np.array_equal(win[k], got99[k]) for k in ("eps", "count", "det"))),
+            "plain_ms_per_step": secp * 1e3,
+            "plain_identical": bool(all(np.array_equal(pl[k], got99[k]) for k in ("eps", "count", "det"))),
             "averaged_det_curve_end": [float(rqa.rqa_averaged_det(d)[-1]) for d in got99["det"]]}
 
 
@@ -352,8 +410,32 @@ def bench_hist(ctx, torch, concat, offs, prm, eps, steps):
                      "Lmax_mean_over_thresholds": float(lmax.astype(np.float64).mean()),
                      "sum_l_P_equals_C": bool(np.array_equal((h * lens).sum(axis=1).astype(np.uint64),
                                                              got["count"]))})
+    # the paper's RR set 1..99 %: selection, DET and the histogram at all 99
+    # thresholds of both series in one call (four histogram passes)
+    rr99 = np.tile(np.arange(1, 100) / 100.0, (len(prm), 1))
+    nvs = [int(offs[i + 1] - offs[i]) - (p[0] - 1) * p[1] for i, p in enumerate(prm)]
+    hl = max(nvs) + 1
+    got = ctx.batch_hist(concat, offs, prm, rr99, hl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = ctx.batch_hist(concat, offs, prm, rr99, hl)
+    call = time.perf_counter() - t0
+    hms = ctx.phase_times()["histogram"]
+    from paper_2208_09136_amd import rqa
+    lens = np.arange(hl, dtype=np.int64)
+    k99 = {"ms_per_call": call * 1e3, "histogram_ms": hms, "series": []}
+    for s_ in range(len(prm)):
+        h = got["hist"][s_].astype(np.int64)
+        L, lmax = rqa.rqa_line_measures(got["hist"][s_], prm[s_][4])
+        k99["series"].append({
+            "sum_l_P_equals_C": bool(np.array_equal((h * lens).sum(axis=1).astype(np.uint64), got["count"][s_])),
+            "averaged_det_99": float(rqa.rqa_averaged_det(got["det"][s_])[-1]),
+            "averaged_L_99": float(rqa.rqa_averaged_det(L)[-1]),
+            "averaged_Lmax_99": float(rqa.rqa_averaged_det(lmax.astype(np.float64))[-1])})
     return {"workload": "each bench series at its 20 selected thresholds, every length kept",
-            "series": rows}
+            "series": rows,
+            "k99_one_call": dict(k99, workload="both bench series, RR 1..99 %: selection + DET + P(l) at every "
+                                               "threshold, one rqa_batch_hist call")}
 
 
 def bench_batch(ctx, torch, rqa, reps=3):
@@ -377,6 +459,13 @@ def bench_batch(ctx, torch, rqa, reps=3):
         out = ctx.batch(concat, offs, prm, rr)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    pl = ctx.batch(concat, offs, prm, rr, flags=rqa.RQA_SEL_PLAIN)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pl = ctx.batch(concat, offs, prm, rr, flags=rqa.RQA_SEL_PLAIN)
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / reps
     singles = [torch.from_numpy(y).to("cuda:0") for y in ys]
     for s in range(3):
         ctx.run(singles[s], prm[s], rr[s])
@@ -391,7 +480,9 @@ def bench_batch(ctx, torch, rqa, reps=3):
     return {"series": len(cases), "pairs": int(cells), "ms": tb * 1e3, "series_per_s": len(cases) / tb,
             "cell_thresholds_per_s": cells * K / tb, "single_calls_ms": ts * 1e3,
             "single_series_per_s": len(cases) / ts, "batched_over_single": ts / tb,
-            "equal_to_single": same, "autotune_chunk_tiles": chunk, "autotune_seconds": t_tune}
+            "equal_to_single": same, "plain_selection_ms": tp * 1e3,
+            "plain_identical": bool(all(np.array_equal(pl[k], out[k]) for k in ("eps", "count", "det"))),
+            "autotune_chunk_tiles": chunk, "autotune_seconds": t_tune}
 
 
 def bench_bracket(ctx, torch, args):
@@ -416,21 +507,111 @@ def bench_bracket(ctx, torch, args):
     return ev
 
 
-def cpu_baseline(case, n_sample):
-    """The CPU oracle (plain C, OpenMP over diagonals) on a prefix of the Lorenz
-    series with the same parameters: exact selection (sort path) and the
-    per-threshold run-length pass."""
+def cpu_model():
+    """CPU model string of the host (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Host threads this process may use (the scheduler's affinity set)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_case(case, method=0):
     import oracle
-    y = case["y"][:n_sample]
-    sub = dict(case, y=y)
+    oracle.run(case["y"], case["m"], case["tau"], case["norm"], case["theiler"], case["lmin"], case["rr"],
+               method=method)
+    return cells_of(case)
+
+
+def time_oracle(cases, workers, budget=None, method=0):
+    """Wall time of the oracle's whole path (selection + lines) on `cases`,
+    independent series running concurrently on `workers` host threads (each
+    call's line passes also use OpenMP).  With a budget in seconds, series
+    are started in the given order until the budget is spent; those started
+    are finished and counted.  Returns (series done, pairs done, seconds)."""
+    import concurrent.futures as cf
     t0 = time.perf_counter()
-    oracle.run(y, case["m"], case["tau"], case["norm"], case["theiler"], case["lmin"], case["rr"])
-    dt = time.perf_counter() - t0
-    cells = cells_of(sub)
-    return {"value": cells * K / dt, "unit": "cell-thresholds/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": dt,
-            "sample": f"first {n_sample} samples of the Lorenz-x 0 dB series, m=3, tau=5, Euclidean, "
-                      f"K=20: {cells} pairs, selection + lines"}
+    done, pairs = 0, 0
+    with cf.ThreadPoolExecutor(workers) as ex:
+        futs = []
+        it = iter(cases)
+        for c in it:
+            futs.append(ex.submit(oracle_case, c, method))
+            if len(futs) >= workers:
+                break
+        pending = set(futs)
+        while pending:
+            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            for f in fin:
+                pairs += f.result()
+                done += 1
+            if budget is None or time.perf_counter() - t0 < budget:
+                for _ in range(len(fin)):
+                    c = next(it, None)
+                    if c is not None:
+                        pending.add(ex.submit(oracle_case, c, method))
+    return done, pairs, time.perf_counter() - t0
+
+
+def cpu_baseline(budget, workers=None):
+    """The CPU oracle as it stands (plain C, qsort selection up to 2e8 pairs
+    and a 31-step bisection above, one run-length pass per threshold, OpenMP
+    over diagonals) on every configuration, independent series running
+    concurrently on all host threads:
+      * the 10 seeds of the N = 10^3 logistic configuration;
+      * all 15 series of the N = 10^4 configuration;
+      * the 600-series ensemble: series in a seeded random order until the
+        budget is spent, with the whole ensemble's time projected from the
+        rate (pairs of the whole ensemble / pairs per second);
+      * the N = 10^5 bench series: the method the oracle takes at that size
+        (bisection) on the first 15,000 samples of both series, projected to
+        the full size linearly in the pairs (every step of that path is a
+        pass over all pairs).  This is `value`, in the bench's unit."""
+    nthreads = host_threads()
+    workers = workers or nthreads
+    out = {"unit": "cell-thresholds/s", "cores": nthreads, "kind": "oracle", "cpu_model": cpu_model(),
+           "omp_num_threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or None}
+    rows = {}
+    small = [synth.config_small(s) for s in range(10)]
+    n, pairs, sec = time_oracle(small, workers)
+    rows["n1e3_logistic_10_seeds"] = {"series": n, "pairs": pairs, "seconds": sec, "value": pairs * K / sec}
+    medium = synth.config_medium()
+    n, pairs, sec = time_oracle(medium, workers)
+    rows["n1e4_15_series"] = {"series": n, "pairs": pairs, "seconds": sec, "value": pairs * K / sec,
+                              "series_per_s": n / sec}
+    ens = synth.config_batch()
+    order = np.random.default_rng(11).permutation(len(ens))
+    total_pairs = sum(cells_of(c) for c in ens)
+    n, pairs, sec = time_oracle([ens[i] for i in order], workers, budget=budget)
+    rate = pairs / sec
+    rows["ensemble_600"] = {"series": n, "pairs": pairs, "seconds": sec, "value": pairs * K / sec,
+                            "series_per_s": n / sec, "ensemble_pairs": total_pairs,
+                            "projected_ensemble_seconds": total_pairs / rate,
+                            "sample": f"{n} of 600 series in a seeded random order, started within {budget} s"}
+    large = synth.config_large()
+    pre = [dict(c, y=c["y"][:15_000]) for c in large]
+    n, pairs, sec = time_oracle(pre, workers, method=2)
+    full = sum(cells_of(c) for c in large)
+    rows["n1e5_bench_series"] = {"series": n, "pairs": pairs, "seconds": sec, "value": pairs * K / sec,
+                                 "method": "bisection", "full_pairs": full,
+                                 "projected_seconds_full_size": sec * full / pairs}
+    out["value"] = rows["n1e5_bench_series"]["value"]
+    out["seconds"] = sum(r["seconds"] for r in rows.values())
+    out["sample"] = ("bench series (N = 1e5, m = 3, tau = 5, Euclidean, K = 20): their first 15,000 samples, "
+                     "bisection selection + lines, both series at once; the other configurations below")
+    out["configs"] = rows
+    return out
 
 
 if __name__ == "__main__":
