@@ -134,6 +134,10 @@ struct rqa_ctx {
     void* static_dev = nullptr;
     bool use_static = false;
     std::vector<unsigned char> static_host;
+    // second stream (default priority) and fork/join events: the variant
+    // groups of one phase run concurrently, the first on the context stream
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // timing
     bool timing = false;
     hipEvent_t ev[2 * PH_N * 8] = {};
@@ -627,6 +631,23 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         ticket += n;
         return t;
     };
+    // The variant groups of one phase (each its own persistent launch) run
+    // concurrently: the first on the context stream, the others on the
+    // second stream, forked from and joined back into the context stream by
+    // events, so the workgroups of one group take the CUs as those of the
+    // other drain instead of each launch ending in its own tail.
+    const bool multi = groups.size() > 1 && c->aux;
+    auto gstream = [&](size_t gi) { return (multi && gi > 0) ? c->aux : sm; };
+    auto fork = [&]() -> hipError_t {
+        if (!multi) return hipSuccess;
+        hipError_t e = hipEventRecord(c->ev_fork, sm);
+        return e != hipSuccess ? e : hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+    };
+    auto join = [&]() -> hipError_t {
+        if (!multi) return hipSuccess;
+        hipError_t e = hipEventRecord(c->ev_join, c->aux);
+        return e != hipSuccess ? e : hipStreamWaitEvent(sm, c->ev_join, 0);
+    };
 
     if (window) {
         WinBufs wb;
@@ -636,7 +657,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         // fused: window pass 1 only; the range sweep resolves the fine bins
         for (int pass = 1; pass <= (fused ? 1 : 2); ++pass) {
             HIP_TRY(tm.begin(pass - 1));
-            for (const Group& g : groups) {
+            HIP_TRY(fork());
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                const Group& g = groups[gi];
                 DevBufs v = view(g);
                 WinBufs wv = wb;
                 wv.bins = wb.bins + (size_t)g.begin * WIN_BINS;
@@ -649,8 +672,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
                 const int t = take(1);
                 if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-                HIP_TRY(launch_window_pass(sm, v, wv, pass, var, grid, block, (uint32_t)t));
+                HIP_TRY(launch_window_pass(gstream(gi), v, wv, pass, var, grid, block, (uint32_t)t));
             }
+            HIP_TRY(join());
             HIP_TRY(tm.end());
             HIP_TRY(tm.begin(PH_OTHER));
             HIP_TRY(launch_window_scan(sm, all, wb, pass));
@@ -660,7 +684,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         // fused: passes 1 and 2; the range sweep takes the place of pass 3
         for (int pass = 1; pass <= (fused ? 2 : 3); ++pass) {
             HIP_TRY(tm.begin(pass - 1));
-            for (const Group& g : groups) {
+            HIP_TRY(fork());
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                const Group& g = groups[gi];
                 DevBufs v = view(g);
                 const int var = g.sel;
                 uint32_t block = 512;
@@ -680,8 +706,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                                               : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
                 const int t = take(ngroups);
                 if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-                HIP_TRY(launch_select_pass(sm, v, pass, var, grid, block, ngroups, G, (uint32_t)t));
+                HIP_TRY(launch_select_pass(gstream(gi), v, pass, var, grid, block, ngroups, G, (uint32_t)t));
             }
+            HIP_TRY(join());
             HIP_TRY(tm.end());
             HIP_TRY(tm.begin(PH_OTHER));
             HIP_TRY(launch_select_scan(sm, all, pass));
@@ -694,6 +721,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         HIP_TRY(tm.end());
         HIP_TRY(tm.begin(PH_HIST));
         const uint32_t kc = job.hist_kp + 1;
+        HIP_TRY(fork());
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const Group& g = groups[gi];
             DevBufs v = view(g);
@@ -705,12 +733,14 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             uint64_t* dg = (uint64_t*)(pool + o_dh) + (size_t)g.begin * job.hist_len * kc;
             uint16_t* pre = (uint16_t*)(pool + o_pre) + g_tile[gi] * kc * TILE_W;
             uint16_t* suf = (uint16_t*)(pool + o_suf) + g_tile[gi] * kc * TILE_W;
-            HIP_TRY(launch_hist(sm, v, g.sel, grid, hist_block, dg, pre, suf, job.hist_len, job.hist_kp, (uint32_t)t));
+            HIP_TRY(launch_hist(gstream(gi), v, g.sel, grid, hist_block, dg, pre, suf, job.hist_len, job.hist_kp,
+                                (uint32_t)t));
             uint32_t items = 1;
             for (uint32_t i = g.begin; i < g.end; ++i) items = std::max(items, sd[i].B * ((job.hist_kp + 3) / 4));
             const uint32_t jgrid = std::min<uint32_t>(items, (uint32_t)c->num_cu * 4);
-            HIP_TRY(launch_hist_join(sm, v, jgrid, pre, suf, dg, job.hist_len, job.hist_kp));
+            HIP_TRY(launch_hist_join(gstream(gi), v, jgrid, pre, suf, dg, job.hist_len, job.hist_kp));
         }
+        HIP_TRY(join());
         HIP_TRY(launch_hist_finish(sm, all, (const uint64_t*)(pool + o_dh), (uint64_t*)(pool + o_hout), job.hist_len,
                                    job.hist_kp));
         HIP_TRY(tm.end());
@@ -721,7 +751,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         else HIP_TRY(launch_sweep_prep(sm, all));
         HIP_TRY(tm.end());
         HIP_TRY(tm.begin(PH_SWEEP));
-        for (const Group& g : groups) {
+        HIP_TRY(fork());
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group& g = groups[gi];
             DevBufs v = view(g);
             const uint32_t block = (!fused && wide_sweep(c, K)) ? 1024 : 512;
             const size_t lds = sweep_lds_bytes(fused ? 2 * K + 1 : K, fused);
@@ -730,8 +762,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
                                           : std::max<uint32_t>(1, std::min<uint32_t>(g.nchunks, (uint32_t)(c->num_cu * per_cu)));
             const int t = take(1);
             if (t < 0) return fail(RQA_ERR_UNSUPPORTED, "too many kernel launches in one call");
-            HIP_TRY(launch_sweep(sm, v, g.swp, fused, grid, block, (uint32_t)t));
+            HIP_TRY(launch_sweep(gstream(gi), v, g.swp, fused, grid, block, (uint32_t)t));
         }
+        HIP_TRY(join());
         HIP_TRY(tm.end());
         if (fused) {
             HIP_TRY(tm.begin(PH_OTHER));
@@ -989,8 +1022,14 @@ void finish_lines(Job& job)
 // with plain selection (14.1 / 14.5 ms at K = 40, 16.6 / 14.6 at 60, 30.2 /
 // 19.1 at 99), between K = 20 and 40 with a window (8.1 / 10.2 ms at K = 20,
 // 13.1 / 11.8 at 40), whose candidate ranges are eight times wider.
-constexpr uint32_t FUSED_MAX_K_PLAIN = 48;
-constexpr uint32_t FUSED_MAX_K_WINDOW = 30;
+#ifndef RQA_FUSED_MAX_K_PLAIN
+#define RQA_FUSED_MAX_K_PLAIN 48
+#endif
+#ifndef RQA_FUSED_MAX_K_WINDOW
+#define RQA_FUSED_MAX_K_WINDOW 30
+#endif
+constexpr uint32_t FUSED_MAX_K_PLAIN = RQA_FUSED_MAX_K_PLAIN;
+constexpr uint32_t FUSED_MAX_K_WINDOW = RQA_FUSED_MAX_K_WINDOW;
 
 bool use_fused(const rqa_ctx* c, uint32_t K, int sel)
 {
@@ -1252,6 +1291,13 @@ rqa_status rqa_create(rqa_ctx** out, int device, void* hip_stream)
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        rqa_destroy(c);
+        return fail(RQA_ERR_DEVICE, "creating the context's second stream or its events failed");
+    }
     *out = c;
     return RQA_OK;
 }
@@ -1268,6 +1314,12 @@ void rqa_destroy(rqa_ctx* c)
     if (c->mlp_partial) (void)hipFree(c->mlp_partial);
     if (c->ev_ready)
         for (auto& e : c->ev) (void)hipEventDestroy(e);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -35,16 +35,27 @@ def sources_digest():
     return h.hexdigest()
 
 
+def short_name(kernel):
+    """Kernel name without its return type and parameter list."""
+    name = kernel[5:] if kernel.startswith("void ") else kernel
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
 def role_of(kernel):
     """Role of a kernel in the step, or None."""
-    if kernel.startswith("rqa::k_select<1,"):
-        return "select_pass1"
-    if kernel.startswith("rqa::k_select<2,"):
-        return "select_pass2"
-    if kernel.startswith("rqa::k_window<1,"):
-        return "window_pass1"
-    if kernel.startswith("rqa::k_range_sweep<"):
-        return "sweep"
+    name = short_name(kernel)
+    for prefix, role in (("rqa::k_select<1,", "select_pass1"), ("rqa::k_select<2,", "select_pass2"),
+                         ("rqa::k_window<1,", "window_pass1"), ("rqa::k_range_sweep<", "sweep")):
+        if name.startswith(prefix):
+            return role
     return None
 
 
@@ -62,19 +73,22 @@ def stats_table(dirname):
             rows += list(csv.DictReader(f))
     out = ["| kernel | calls | total us | average us | % |", "|---|---:|---:|---:|---:|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        out.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     return "\n".join(out)
 
 
 def counter_means(dirname):
-    """{kernel name: {counter: mean per dispatch}} of one --pmc run."""
+    """{kernel name: {counter: mean per dispatch}} of one --pmc run; for the
+    device copy kernel, which also moves the small per-call descriptors, the
+    largest dispatch (the calibration copy)."""
     acc = defaultdict(lambda: defaultdict(list))
     for path in find(dirname, "_counter_collection.csv"):
         with open(path) as f:
             for r in csv.DictReader(f):
                 acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    return {k: {c: (max(v) if k == COPY_KERNEL else sum(v) / len(v)) for c, v in cs.items()}
+            for k, cs in acc.items()}
 
 
 def counters(out_json, sq_dir, fetch_dir, write_dir, copy_bytes):
@@ -87,7 +101,7 @@ def counters(out_json, sq_dir, fetch_dir, write_dir, copy_bytes):
         role = role_of(name)
         if role is None:
             continue
-        k = {"kernel": name, "valu_insts": cs.get("SQ_INSTS_VALU"), "salu_insts": cs.get("SQ_INSTS_SALU"),
+        k = {"kernel": short_name(name), "valu_insts": cs.get("SQ_INSTS_VALU"), "salu_insts": cs.get("SQ_INSTS_SALU"),
              "lds_insts": cs.get("SQ_INSTS_LDS"), "active_inst_valu": cs.get("SQ_ACTIVE_INST_VALU"),
              "wait_inst_lds": cs.get("SQ_WAIT_INST_LDS"), "lds_bank_conflict": cs.get("SQ_LDS_BANK_CONFLICT"),
              "busy_cycles": cs.get("SQ_BUSY_CYCLES"), "gui_active": cs.get("GRBM_GUI_ACTIVE")}
