@@ -986,7 +986,7 @@ __device__ __forceinline__ uint32_t rho_of(uint32_t u, const RhoCtx& c)
 // (x, y) and the rank base z (z + boundaries below the bucket); w > 0 marks a
 // bucket with w > 2 boundaries, compared one by one (rare).
 struct RangeCtx {
-    const uint4* table;     // LDS [RANGE_TABLE]
+    const uint4* table;     // LDS [RANGE_TABLE], at LDS byte 0
     const uint32_t* es;     // LDS [Kp] boundaries
     float emin, emax;
     uint32_t sh4, Kp, z;    // sh4 = bucket shift - 4 (the shift is at least 4)
@@ -1003,12 +1003,16 @@ __device__ __forceinline__ uint32_t rank_of(uint32_t u, const RangeCtx& c)
 {
     const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
     const uint32_t off = (cl >> c.sh4) & ((RANGE_TABLE - 1u) << 4);
-    const uint4 e = *(const uint4*)((const unsigned char*)c.table + off);
-    uint32_t r = e.z + ((e.x - u) >> 31) + ((e.y - u) >> 31);
+    // the table sits at LDS byte 0 (k_range_sweep checks it), so its byte
+    // offset is the LDS address: no base to add per key
+    const __attribute__((address_space(3))) uint32_t* e = (const __attribute__((address_space(3))) uint32_t*)(size_t)off;
+    const uint32_t ex = e[0], ey = e[1], ez = e[2];
+    uint32_t r = ez + ((ex - u) >> 31) + ((ey - u) >> 31);
     if constexpr (MULTI) {
-        if (e.w) {
-            r = e.z;
-            for (uint32_t i = 0; i < e.w; ++i) r += (u > c.es[e.z - c.z + i]) ? 1u : 0u;
+        const uint32_t ew = e[3];
+        if (ew) {
+            r = ez;
+            for (uint32_t i = 0; i < ew; ++i) r += (u > c.es[ez - c.z + i]) ? 1u : 0u;
         }
     }
     return r;
@@ -1465,6 +1469,14 @@ k_range_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, 
     body.nfine = 0;
     body.multi = false;
     body.lmin = LMC == 0 ? sds[0].lmin : (uint32_t)LMC;
+    // rank_of addresses the rank table by its offset from LDS byte 0: the
+    // kernel's dynamic LDS must start there (it has no static LDS); a launch
+    // where it does not marks every series (the host reports a device error)
+    if ((uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)smem != 0u) {
+        if (threadIdx.x == 0)
+            for (uint32_t s = 0; s < S; ++s) atomicOr(&works[s].status, 64u);
+        return;
+    }
     chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + sweep_lds_bytes_dev(rows, true)));
 }
 
@@ -2341,7 +2353,13 @@ struct WinPass1 {
     // divergence.
     __device__ __forceinline__ void count(uint32_t u, uint32_t)
     {
-        if (u <= hi) atomicAdd(&bins[__builtin_elementwise_sub_sat(u, base) >> shift], 1u);
+        // the bins sit at LDS byte 0 (k_window checks it): the bin's byte
+        // offset is its LDS address
+        if (u <= hi) {
+            const uint32_t a = (__builtin_elementwise_sub_sat(u, base) >> shift) << 2;
+            __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(size_t)a, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
     __device__ void tile(const SeriesScalars& sd, uint32_t tile_id, int lane)
     {
@@ -2403,6 +2421,14 @@ k_window(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint3
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* slot = (uint32_t*)(smem + window_lds_bytes_dev(PASS) - 16);
     if constexpr (PASS == 1) {
+        // WinPass1 addresses its bins by their offset from LDS byte 0: the
+        // kernel's dynamic LDS must start there (it has no static LDS); a
+        // launch where it does not marks every series (a device error)
+        if ((uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)smem != 0u) {
+            if (threadIdx.x == 0)
+                for (uint32_t s = 0; s < S; ++s) atomicOr(&works[s].status, 64u);
+            return;
+        }
         WinPass1<NORM, MC, TC> body;
         body.bins = (uint32_t*)smem;
         body.gbins = bins;
