@@ -481,8 +481,14 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     size_t off = 0;
     auto carve = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_sd = carve(sizeof(SeriesDesc) * S);
-    const size_t o_work = carve(sizeof(SeriesWork) * S);
+    const size_t o_tgt = carve(sizeof(uint64_t) * S * K);
+    const bool lines_out = (job.mode & MODE_SWEEP) != 0;
+    const size_t res_words = result_words(K, lines_out);
+    const size_t o_res = carve(sizeof(uint64_t) * S * res_words);
     const size_t o_tick = carve(sizeof(uint32_t) * NUM_TICKETS);
+    // the working state is cleared with the tickets and histograms; the
+    // targets are placed into it on the device
+    const size_t o_work = carve(sizeof(SeriesWork) * S);
     const size_t o_h1 = carve(sizeof(uint64_t) * S * SEL_N1);
     const size_t o_h2 = carve(sizeof(uint64_t) * S * K * SEL_N2);
     const size_t o_h3 = carve(sizeof(uint64_t) * S * K * SEL_N3);
@@ -549,10 +555,12 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     all.chunk_tiles = CT;
     all.nchunks = 0;
 
-    // host staging: descriptors + work (in), work (out), sketch features (out)
-    const size_t hs_sd = sizeof(SeriesDesc) * S, hs_work = sizeof(SeriesWork) * S;
+    // host staging: descriptors and targets (in), packed results and sketch
+    // features (out)
+    const size_t hs_sd = sizeof(SeriesDesc) * S, hs_tgt = sizeof(uint64_t) * S * K;
+    const size_t hs_res = sizeof(uint64_t) * S * res_words;
     const size_t hs_feat = (job.mode & MODE_SKETCH) ? sizeof(float) * S * SKETCH_FEATURES : 0;
-    const size_t hs_all = hs_sd + 2 * hs_work + hs_feat + sizeof(float) * MLP_OUT;
+    const size_t hs_all = hs_sd + hs_tgt + hs_res + hs_feat + sizeof(float) * MLP_OUT;
     char* hbase = nullptr;
     if (c->use_static) {
         // ordinary host memory (no pinned allocation); the copies below then
@@ -564,30 +572,29 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         hbase = (char*)c->host;
     }
     SeriesDesc* h_sd = (SeriesDesc*)hbase;
-    SeriesWork* h_work = (SeriesWork*)(hbase + hs_sd);
-    SeriesWork* h_out = (SeriesWork*)(hbase + hs_sd + hs_work);
-    float* h_feat = (float*)(hbase + hs_sd + 2 * hs_work);
-    float* h_delta = (float*)(hbase + hs_sd + 2 * hs_work + hs_feat);
+    uint64_t* h_tgt = (uint64_t*)(hbase + hs_sd);
+    uint64_t* h_res = (uint64_t*)(hbase + hs_sd + hs_tgt);
+    float* h_feat = (float*)(hbase + hs_sd + hs_tgt + hs_res);
+    float* h_delta = (float*)(hbase + hs_sd + hs_tgt + hs_res + hs_feat);
     std::memcpy(h_delta, c->bracket_delta, sizeof(float) * MLP_OUT);
     if (window && job.sel == 1 && !c->has_model)
         return fail(RQA_ERR_INVALID_ARG, "RQA_SEL_LEARNED needs a network (rqa_mlp_init / rqa_mlp_set_params)");
     std::memcpy(h_sd, sd.data(), hs_sd);
-    std::memset(h_work, 0, hs_work);
+    const bool as_rank = (job.mode & MODE_SELECT) != 0;
+    const bool has_tgt = as_rank || (job.mode & (MODE_SWEEP | MODE_HIST));
     for (uint32_t i = 0; i < S; ++i) {
         const uint32_t s = order[i];
-        for (uint32_t r = 0; r < K; ++r) {
-            if (job.mode & MODE_SELECT) h_work[i].k[r] = job.k[(size_t)s * K + r];
-            else if (job.mode & (MODE_SWEEP | MODE_HIST)) h_work[i].eps_bits[r] = job.eps_bits[(size_t)s * K + r];
-        }
+        for (uint32_t r = 0; r < K; ++r)
+            h_tgt[(size_t)i * K + r] = !has_tgt ? 0 : as_rank ? job.k[(size_t)s * K + r] : job.eps_bits[(size_t)s * K + r];
     }
 
     Timer tm(c);
     hipStream_t sm = c->stream;
     HIP_TRY(tm.begin(PH_OTHER));
     HIP_TRY(hipMemcpyAsync(all.sd, h_sd, hs_sd, hipMemcpyHostToDevice, sm));
-    HIP_TRY(hipMemcpyAsync(all.work, h_work, hs_work, hipMemcpyHostToDevice, sm));
+    HIP_TRY(hipMemcpyAsync(pool + o_tgt, h_tgt, hs_tgt, hipMemcpyHostToDevice, sm));
     HIP_TRY(launch_zero(sm, pool + o_tick, zero_end - o_tick));
-    HIP_TRY(launch_check_finite(sm, all, maxn));
+    HIP_TRY(launch_check_finite(sm, all, maxn, (const uint64_t*)(pool + o_tgt), as_rank));
     if (sketch)
         HIP_TRY(launch_sketch(sm, all, (float*)(pool + o_feat), window ? (uint32_t*)(pool + o_smp) : nullptr));
     if (window) {
@@ -772,7 +779,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
             HIP_TRY(tm.end());
         }
     }
-    HIP_TRY(hipMemcpyAsync(h_out, all.work, hs_work, hipMemcpyDeviceToHost, sm));
+    HIP_TRY(launch_pack_results(sm, all, lines_out, (uint64_t*)(pool + o_res)));
+    HIP_TRY(hipMemcpyAsync(h_res, pool + o_res, hs_res, hipMemcpyDeviceToHost, sm));
     if (hs_feat) HIP_TRY(hipMemcpyAsync(h_feat, pool + o_feat, hs_feat, hipMemcpyDeviceToHost, sm));
     if (hist) {
         // rows straight into the caller's buffer, series back in caller order
@@ -802,37 +810,48 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     if (window) job.hit.assign((size_t)S * K, 0);
     for (uint32_t i = 0; i < S; ++i) {
         const uint32_t s = order[i];
-        const SeriesWork& w = h_out[i];
-        if (w.nonfinite) return fail(RQA_ERR_NONFINITE, "series %u holds a NaN or infinite sample", s);
-        if (w.status & ~8u) return fail(RQA_ERR_DEVICE, "selection of series %u is inconsistent (code %u)", s, w.status);
+        // packed results of device series i (layout at k_pack_results)
+        const uint64_t* w = h_res + (size_t)i * res_words;
+        const uint32_t status = (uint32_t)w[0], nonfinite = (uint32_t)(w[0] >> 32);
+        const uint32_t scale = (uint32_t)w[1], range_ok = (uint32_t)(w[1] >> 32);
+        const uint64_t* w_eps = w + 3;
+        const uint64_t* w_k = w_eps + K;
+        const uint64_t* w_count = w_k + K;
+        const uint64_t* w_dcount = w_count + K;
+        const uint64_t* w_hitmap = w_dcount + K;
+        if (nonfinite) return fail(RQA_ERR_NONFINITE, "series %u holds a NaN or infinite sample", s);
+        if (status & ~8u) return fail(RQA_ERR_DEVICE, "selection of series %u is inconsistent (code %u)", s, status);
         if (job.mode & MODE_SKETCH) {
             std::memcpy(&job.features[(size_t)s * SKETCH_FEATURES], h_feat + (size_t)i * SKETCH_FEATURES,
                         sizeof(float) * SKETCH_FEATURES);
-            job.scale[s] = w.scale;
+            job.scale[s] = scale;
         }
         for (uint32_t r = 0; r < K; ++r) {
             float e;
-            std::memcpy(&e, &w.eps_bits[r], 4);
+            const uint32_t bits = (uint32_t)w_eps[r];
+            std::memcpy(&e, &bits, 4);
             job.eps[(size_t)s * K + r] = e;
-            job.kout[(size_t)s * K + r] = w.k[r];
-            job.count_sel[(size_t)s * K + r] = w.count[r];
-            if (fused) job.dcount[(size_t)s * K + r] = job.series[s].p.lmin <= 1 ? w.count[r] : w.dcount[r];
+            job.kout[(size_t)s * K + r] = w_k[r];
+            job.count_sel[(size_t)s * K + r] = w_count[r];
+            if (fused) job.dcount[(size_t)s * K + r] = job.series[s].p.lmin <= 1 ? w_count[r] : w_dcount[r];
             // fused window mode resolves a series only when every target hit
-            if (window) job.hit[(size_t)s * K + r] = (w.win_hit[r] && (!fused || w.range_ok)) ? 1 : 0;
+            if (window) job.hit[(size_t)s * K + r] = ((uint32_t)w_hitmap[r] && (!fused || range_ok)) ? 1 : 0;
         }
         if (job.mode & MODE_SWEEP) {
-            const uint32_t Kp = w.Kp;
+            const uint32_t Kp = (uint32_t)w[2];
+            const uint64_t* w_hrho = w_hitmap + K;
+            const uint64_t* w_hlam = w_hrho + K;
             std::vector<uint64_t> C(Kp), D(Kp);
             uint64_t cr = 0, cl = 0;
             for (uint32_t j = 0; j < Kp; ++j) {
-                cr += w.hrho[j];
-                cl += w.hlam[j];
+                cr += w_hrho[j];
+                cl += w_hlam[j];
                 C[j] = cr;
                 D[j] = cl;
             }
             double sum = 0.0;
             for (uint32_t r = 0; r < K; ++r) {
-                const uint32_t j = w.dmap[r];
+                const uint32_t j = (uint32_t)(w_hitmap[r] >> 32);
                 const uint64_t cnt = C[j];
                 const double det = cnt ? (double)D[j] / (double)cnt : NAN;
                 job.count[(size_t)s * K + r] = cnt;

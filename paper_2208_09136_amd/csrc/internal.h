@@ -154,7 +154,13 @@ constexpr int NUM_TICKETS = 256;
 
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_zero(hipStream_t st, void* p, size_t bytes);
-hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn);
+// Flags non-finite samples and places the targets tgt[S][K] (ranks when
+// as_rank, else threshold bit patterns) into the zeroed working state.
+hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn, const uint64_t* tgt, bool as_rank);
+// Results the host reads, result_words(K, lines) words per series (layout at
+// k_pack_results).
+__host__ __device__ __forceinline__ size_t result_words(uint32_t K, bool lines) { return 3 + (size_t)(lines ? 7 : 5) * K; }
+hipError_t launch_pack_results(hipStream_t st, const DevBufs& b, bool lines, uint64_t* out);
 hipError_t launch_select_pass(hipStream_t st, const DevBufs& b, int pass, int variant,
                               uint32_t grid, uint32_t block, uint32_t groups, uint32_t group_slots,
                               uint32_t ticket_base);

@@ -272,21 +272,65 @@ hipError_t launch_zero(hipStream_t st, void* p, size_t bytes)
     return hipGetLastError();
 }
 
-__global__ void k_check_finite(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works)
+// Per series: flags a NaN or infinite sample, and (block x = 0) places the
+// call's targets into the zeroed working state: tgt[s * K + r] is target r's
+// rank (selection) or threshold bit pattern (given thresholds).
+__global__ void k_check_finite(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                               const uint64_t* __restrict__ tgt, uint32_t K, uint32_t as_rank)
 {
     const SeriesDesc& sd = sds[blockIdx.y];
+    SeriesWork& w = works[blockIdx.y];
+    if (blockIdx.x == 0 && tgt) {
+        for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+            const uint64_t v = tgt[(size_t)blockIdx.y * K + r];
+            if (as_rank) w.k[r] = v;
+            else w.eps_bits[r] = (uint32_t)v;
+        }
+    }
     bool bad = false;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sd.n; i += gridDim.x * blockDim.x) {
         const uint32_t u = __float_as_uint(sd.y[i]);
         bad |= (u & 0x7F800000u) == 0x7F800000u;
     }
-    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&works[blockIdx.y].nonfinite, 1u);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&w.nonfinite, 1u);
 }
 
-hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn)
+hipError_t launch_check_finite(hipStream_t st, const DevBufs& b, uint32_t maxn, const uint64_t* tgt, bool as_rank)
 {
     uint32_t gx = std::min<uint32_t>((maxn + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_check_finite, dim3(gx, b.S), dim3(256), 0, st, b.sd, b.work);
+    hipLaunchKernelGGL(k_check_finite, dim3(gx, b.S), dim3(256), 0, st, b.sd, b.work, tgt, b.K, as_rank ? 1u : 0u);
+    return hipGetLastError();
+}
+
+// The results the host reads, packed per series into result_words(K, lines)
+// 64-bit words: [0] status | nonfinite << 32, [1] scale | range_ok << 32,
+// [2] Kp, then K words each of eps_bits, k, count, dcount, win_hit | dmap
+// << 32, and with lines (threshold sweep) Kp words each of hrho and hlam.
+__global__ void k_pack_results(const SeriesWork* __restrict__ works, uint32_t K, uint32_t lines, uint64_t* __restrict__ out)
+{
+    const SeriesWork& w = works[blockIdx.x];
+    uint64_t* o = out + (size_t)blockIdx.x * result_words(K, lines != 0);
+    if (threadIdx.x == 0) {
+        o[0] = (uint64_t)w.status | ((uint64_t)w.nonfinite << 32);
+        o[1] = (uint64_t)w.scale | ((uint64_t)w.range_ok << 32);
+        o[2] = w.Kp;
+    }
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        o[3 + r] = w.eps_bits[r];
+        o[3 + K + r] = w.k[r];
+        o[3 + 2 * K + r] = w.count[r];
+        o[3 + 3 * K + r] = w.dcount[r];
+        o[3 + 4 * K + r] = (uint64_t)w.win_hit[r] | ((uint64_t)w.dmap[r] << 32);
+        if (lines) {
+            o[3 + 5 * K + r] = w.hrho[r];
+            o[3 + 6 * K + r] = w.hlam[r];
+        }
+    }
+}
+
+hipError_t launch_pack_results(hipStream_t st, const DevBufs& b, bool lines, uint64_t* out)
+{
+    hipLaunchKernelGGL(k_pack_results, dim3(b.S), dim3(64), 0, st, b.work, b.K, lines ? 1u : 0u, out);
     return hipGetLastError();
 }
 
