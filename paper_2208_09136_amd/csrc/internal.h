@@ -127,7 +127,10 @@ struct SeriesWork {
 // of a CU as 32-bit counters, one workgroup of 1024 threads per CU); the last
 // win_shift <= WIN_MAX_SHIFT bits are resolved by the range sweep or a second
 // window pass.
-constexpr uint32_t WIN_BINS = 39 * 1024;
+#ifndef RQA_WIN_BINS
+#define RQA_WIN_BINS (39 * 1024)
+#endif
+constexpr uint32_t WIN_BINS = RQA_WIN_BINS;
 constexpr uint32_t WIN_BLOCK = 1024;
 constexpr uint32_t WIN_MAX_SHIFT = 13;
 
