@@ -1034,18 +1034,19 @@ void finish_lines(Job& job)
 // at them follows.  stat_passes counts every full pass over the pairs.
 // The range sweep (counting passes, then ranks against the candidate ranges
 // left by them) while it is the faster path, else complete selection and the
-// threshold sweep.  The range sweep's cost grows with K (a per-lane
-// line-rank histogram of 2K + 1 rows in LDS, and more keys inside candidate
-// ranges take its fine-counter path), the threshold sweep's hardly does.
-// Measured crossovers on MI355X (two N = 1e5 series): between K = 40 and 60
-// with plain selection (14.1 / 14.5 ms at K = 40, 16.6 / 14.6 at 60, 30.2 /
-// 19.1 at 99), between K = 20 and 40 with a window (8.1 / 10.2 ms at K = 20,
-// 13.1 / 11.8 at 40), whose candidate ranges are eight times wider.
+// threshold sweep.  The range sweep's cost grows with K (line-rank histograms
+// of 2K + 1 rows in LDS, which keep three workgroups per CU up to K = 76, and
+// more keys inside candidate ranges take its fine-counter path), the
+// threshold sweep's hardly does.  Measured on MI355X (two N = 1e5 series,
+// targets 1..K %, range sweep / complete selection, ms per step): plain
+// selection 12.7 / 13.6 at K = 56, 13.4 / 13.8 at 64, 14.1 / 14.1 at 72,
+// 17.5 / 14.5 at 80; with the sample window, whose candidate ranges are
+// wider, 8.9 / 9.5 at K = 36, 9.4 / 9.6 at 40, 10.5 / 9.8 at 48.
 #ifndef RQA_FUSED_MAX_K_PLAIN
-#define RQA_FUSED_MAX_K_PLAIN 48
+#define RQA_FUSED_MAX_K_PLAIN 64
 #endif
 #ifndef RQA_FUSED_MAX_K_WINDOW
-#define RQA_FUSED_MAX_K_WINDOW 30
+#define RQA_FUSED_MAX_K_WINDOW 40
 #endif
 constexpr uint32_t FUSED_MAX_K_PLAIN = RQA_FUSED_MAX_K_PLAIN;
 constexpr uint32_t FUSED_MAX_K_WINDOW = RQA_FUSED_MAX_K_WINDOW;

@@ -727,13 +727,20 @@ hipError_t launch_select_pass(hipStream_t st, const DevBufs& b, int pass, int va
     return hipGetLastError();
 }
 
-int select_blocks_per_cu(int pass, int variant, uint32_t block, size_t lds)
+// Workgroups of `block` threads with `lds` bytes of dynamic LDS that one CU
+// runs at once: the runtime's occupancy query, capped by the LDS allocation
+// unit it does not apply.
+int blocks_per_cu(const void* f, uint32_t block, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_fn_pass(pass, variant), (int)block, lds) !=
-        hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, (int)block, lds) != hipSuccess || n < 1) return 1;
+    const int fit = (int)lds_blocks_fit(lds);
+    return n < fit ? n : (fit > 0 ? fit : 1);
+}
+
+int select_blocks_per_cu(int pass, int variant, uint32_t block, size_t lds)
+{
+    return blocks_per_cu((const void*)select_fn_pass(pass, variant), block, lds);
 }
 
 // ------------------------------------------------------------------ scans
@@ -1226,13 +1233,31 @@ struct SweepBody {
 // line values inside it.  A key or line value inside a group adds one to
 // the group's fine counter at its offset from the group start (global
 // memory, rare).  lmin = 1 needs no line values (D = C).
+// Range-sweep LDS: rank table (at byte 0), per-column line-rank histograms
+// of rows + 1 rows, the boundaries, then the group starts and fine offsets.
+// A histogram row has 64 columns (one per lane) or, where 64 would cost a
+// CU its third workgroup, 32 (lanes L and L + 32 share a column): the third
+// workgroup is worth more than the shared columns cost (K = 48: sweep 7.36
+// -> 6.07 ms; K = 20, where both layouts fit three: 64 columns 0.3% faster).
+__host__ __device__ __forceinline__ size_t range_lds_layout(uint32_t rows, uint32_t cols)
+{
+    return RANGE_TABLE * sizeof(uint4) + (size_t)(rows + 1) * cols * 4 + (size_t)(rows - 1) * 4 +
+           2 * (size_t)((rows + 1) / 2 + 1) * 4;
+}
+__host__ __device__ __forceinline__ uint32_t range_cols(uint32_t rows)
+{
+    return lds_blocks_fit(range_lds_layout(rows, 64) + 16) >= 3 ? 64u : 32u;
+}
+
 template <int NORM, int MC, int TC, int LMC>
 struct RangeBody {
-    uint4* stab;          // LDS [RANGE_TABLE]
-    uint32_t* ses;        // LDS [RANK_MAX]
-    uint32_t* blam;       // LDS [rows+1][64]: the last row collects cells outside the diagonal
-    uint32_t* sglo;       // LDS [RQA_MAX_K + 1] group starts
-    uint32_t* sgoff;      // LDS [RQA_MAX_K + 1] group fine offsets
+    uint4* stab;          // LDS [RANGE_TABLE], at byte 0
+    uint32_t* blam;       // LDS [rows+1][cols]: the last row collects cells outside the diagonal
+    uint32_t* ses;        // LDS [rows - 1] boundaries (rows - 1 = 2K >= Kp)
+    uint32_t* sglo;       // LDS [gcap] group starts (gcap = K + 2 > ngroups)
+    uint32_t* sgoff;      // LDS [gcap] group fine offsets
+    uint32_t cols, csh, gcap;  // histogram columns, log2 of a row's bytes
+    uint32_t lcol;        // this lane's column byte offset
     const uint4* rtab;    // global [S][RANGE_TABLE]
     SeriesWork* works;
     uint64_t* fineK;      // global [S][fine_stride]
@@ -1253,9 +1278,9 @@ struct RangeBody {
         const SeriesWork& w = works[s];
         active = uniform(w.range_ok) != 0;
         for (uint32_t i = threadIdx.x; i < RANGE_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RANGE_TABLE + i];
-        for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) ses[i] = w.esorted[i];
-        for (uint32_t i = threadIdx.x; i < (rows + 1) * TILE_W; i += blockDim.x) blam[i] = 0u;
-        for (uint32_t i = threadIdx.x; i <= RQA_MAX_K; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x; i < rows - 1; i += blockDim.x) ses[i] = w.esorted[i];
+        for (uint32_t i = threadIdx.x; i < (rows + 1) * cols; i += blockDim.x) blam[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < gcap; i += blockDim.x) {
             sglo[i] = w.g_lo[i];
             sgoff[i] = w.g_off[i];
         }
@@ -1278,13 +1303,17 @@ struct RangeBody {
         if (!active || LMC == 1) return;
         SeriesWork& w = works[s];
         for (uint32_t j = threadIdx.x; j < spare; j += blockDim.x) {
-            const uint32_t* row = blam + j * TILE_W;
+            const uint32_t* row = blam + j * cols;
             uint64_t sum = 0;
-            for (int l = 0; l < TILE_W; ++l) sum += row[l];
+            for (uint32_t l = 0; l < cols; ++l) sum += row[l];
             if (sum) atomicAdd((unsigned long long*)&w.hlam[j], (unsigned long long)sum);
         }
     }
-    __device__ __forceinline__ void emit(uint32_t lam, int lane) const { atomicAdd(&blam[lam * TILE_W + lane], 1u); }
+    // row lam, this lane's column: one shift-and-add for the byte offset
+    __device__ __forceinline__ void emit(uint32_t lam, int) const
+    {
+        atomicAdd((uint32_t*)((unsigned char*)blam + ((lam << csh) + lcol)), 1u);
+    }
     // count value x of rank r if r is odd (inside group r/2); group and
     // counter index are checked, so no rank can address outside the counters
     __device__ __forceinline__ void fine(unsigned long long* dst, uint32_t r, uint32_t x) const
@@ -1457,7 +1486,7 @@ struct RangeBody {
 __host__ __device__ __forceinline__ size_t sweep_lds_bytes_dev(uint32_t rows, bool ranges)
 {
     if (ranges)
-        return RANGE_TABLE * sizeof(uint4) + RANK_MAX * 4 + (size_t)(rows + 1) * TILE_W * 4 + 2 * (RQA_MAX_K + 1) * 4;
+        return range_lds_layout(rows, range_cols(rows));
     return RHO_TABLE * sizeof(uint2) + RANK_MAX * 4 + 2 * (size_t)(rows + 1) * TILE_W * 4;
 }
 
@@ -1485,7 +1514,8 @@ k_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32
 }
 
 // Six waves per SIMD (three workgroups of 512 per CU, which the LDS allows up
-// to K = 40 or so): the register budget drops to 80 and a few spill, but the
+// to K = 38 with 64 histogram columns and up to K = 76 with 32, in 1280-byte
+// units): the register budget drops to 80 and a few spill, but the
 // extra waves hide the rank-table and series loads better (about 10% faster
 // at K = 20 than the four waves 105 registers allow).
 template <int NORM, int MC, int TC, int LMC>
@@ -1496,11 +1526,15 @@ k_range_sweep(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, 
 {
     extern __shared__ __align__(16) unsigned char smem[];
     RangeBody<NORM, MC, TC, LMC> body;
+    body.cols = range_cols(rows);
+    body.csh = body.cols == 64 ? 8u : 7u;
+    body.gcap = (rows + 1) / 2 + 1;
+    body.lcol = ((uint32_t)threadIdx.x & (body.cols - 1)) * 4u;
     body.stab = (uint4*)smem;
-    body.ses = (uint32_t*)(smem + RANGE_TABLE * sizeof(uint4));
-    body.blam = body.ses + RANK_MAX;
-    body.sglo = body.blam + (size_t)(rows + 1) * TILE_W;
-    body.sgoff = body.sglo + (RQA_MAX_K + 1);
+    body.blam = (uint32_t*)(smem + RANGE_TABLE * sizeof(uint4));
+    body.ses = body.blam + (size_t)(rows + 1) * body.cols;
+    body.sglo = body.ses + (rows - 1);
+    body.sgoff = body.sglo + body.gcap;
     body.rtab = (const uint4*)rtab;
     body.works = works;
     body.fineK = fineK;
@@ -1601,10 +1635,7 @@ hipError_t launch_sweep(hipStream_t st, const DevBufs& b, int variant, bool rang
 
 int sweep_blocks_per_cu(int variant, bool ranges, uint32_t block, size_t lds)
 {
-    int n = 0;
-    const void* f = ranges ? (const void*)range_fn(variant) : (const void*)sweep_fn(variant);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, (int)block, lds) != hipSuccess) return 1;
-    return n > 0 ? n : 1;
+    return blocks_per_cu(ranges ? (const void*)range_fn(variant) : (const void*)sweep_fn(variant), block, lds);
 }
 
 // Rank table of one series over the ascending thresholds es[0..kp) with rank
@@ -1739,13 +1770,20 @@ struct HistBody {
     // its position), so runs of such cells cost no pops.  Only the segment's own
     // sentinel has position t0.
     uint32_t top, nx, so, so0, so1, bd4, pm, t0;
+    uint32_t sh3;         // bucket shift - 3
     uint16_t* lpre;       // this lane's pre / suf column in the current tile
     uint16_t* lsuf;
 
     __device__ __forceinline__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
-        for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) stab[i] = rtab[(size_t)s * RHO_TABLE + i];
+        // an empty bucket's first threshold becomes 0x7FFFFFFF (above every
+        // key, and b - u cannot wrap): see rank()
+        for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) {
+            uint2 e = rtab[(size_t)s * RHO_TABLE + i];
+            e.x = min(e.x, 0x7FFFFFFFu);
+            stab[i] = e;
+        }
         for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) ses[i] = w.esorted[i];
         for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) dsh[i] = 0u;
         rc.table = stab;
@@ -1755,7 +1793,10 @@ struct HistBody {
         rc.shift = uniform(w.shift);
         rc.Kp = uniform(w.Kp);
         rc.z = 0;
-        multi = uniform(w.multi) != 0;
+        // rank() needs a bucket shift of at least 3; narrower tables take the
+        // general lookup
+        multi = uniform(w.multi) != 0 || rc.shift < 3u;
+        sh3 = rc.shift - 3u;
         active = uniform(w.nonfinite) == 0u;  // no ranks for a series with NaN or infinite samples
         dser = dglob + (size_t)s * hist_len * kcap;
         tbase = uniform(sds[s].chunk_begin) * chunk_tiles;
@@ -1789,6 +1830,22 @@ struct HistBody {
         // row 0 is the bottom sentinel: below it is the sentinel again
         nx = at(so - bd4);
         so = max(so - bd4, so1);
+    }
+    // Rank of a key (at most Kp).  Without a multi-threshold bucket: the
+    // bucket's byte offset as a right shift and a mask (the table sits at LDS
+    // byte 0, k_hist checks it), and the compare as the sign bit of b - u
+    // (keys are at most 0x7F800000, an empty bucket's b is 0x7FFFFFFF).
+    template <bool MULTI>
+    __device__ __forceinline__ uint32_t rank(uint32_t u, const RhoCtx& c) const
+    {
+        if constexpr (MULTI) {
+            return rho_of<true>(u, c);
+        } else {
+            const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
+            const uint32_t off = (cl >> sh3) & ((RHO_TABLE - 1u) << 3);
+            const __attribute__((address_space(3))) uint32_t* e = (const __attribute__((address_space(3))) uint32_t*)(size_t)off;
+            return e[1] + ((e[0] - u) >> 31);
+        }
     }
     // cell of rank r <= Kp at position t
     __device__ __forceinline__ void cell(uint32_t r, uint32_t t)
@@ -1850,7 +1907,7 @@ struct HistBody {
                 walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                     uint32_t rk[HU];
 #pragma unroll
-                    for (int u = 0; u < HU; ++u) rk[u] = min(rho_of<MULTI>(k[u], c), Kp);
+                    for (int u = 0; u < HU; ++u) rk[u] = rank<MULTI>(k[u], c);
 #pragma unroll
                     for (int u = 0; u < HU; ++u)
                         if (u < valid) cell(rk[u], t + (uint32_t)u);
@@ -1913,6 +1970,12 @@ k_hist(const SeriesDesc* __restrict__ sds, uint32_t S, uint32_t nchunks, uint32_
     body.kcap = Kp + 1;
     body.chunk_tiles = chunk_tiles;
     body.multi = false;
+    // rank() addresses the rank table by its offset from LDS byte 0
+    if ((uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)smem != 0u) {
+        if (threadIdx.x == 0)
+            for (uint32_t s = 0; s < S; ++s) atomicOr(&works[s].status, 64u);
+        return;
+    }
     chunk_loop(sds, S, nchunks, chunk_tiles, ticket, body, (uint32_t*)(smem + hist_lds_bytes_dev(Kp, blockDim.x)));
 }
 
@@ -2054,11 +2117,7 @@ hipError_t launch_hist_join(hipStream_t st, const DevBufs& b, uint32_t grid, con
 
 int hist_blocks_per_cu(int select_variant, uint32_t Kp, uint32_t block)
 {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hist_fn(select_variant), (int)block,
-                                                     hist_lds_bytes(Kp, block)) != hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
+    return blocks_per_cu((const void*)hist_fn(select_variant), block, hist_lds_bytes(Kp, block));
 }
 
 
@@ -2280,7 +2339,9 @@ __device__ void set_window(SeriesWork& w, int64_t lo, int64_t hi, bool valid)
         return;
     }
     const uint32_t span = (uint32_t)(hi - lo);
-    uint32_t sh = 0;
+    // at least 2: window pass 1 forms a bin's byte offset as a right shift
+    // by win_shift - 2 and a mask
+    uint32_t sh = 2;
     while (sh < 31 && (span >> sh) >= WIN_BINS) ++sh;
     w.win_lo = (uint32_t)lo;
     w.win_span = span;
@@ -2368,13 +2429,14 @@ struct WinPass1 {
     uint64_t* gbins;      // global [S][WIN_BINS]
     SeriesWork* works;
     uint32_t base;        // win_lo - 2^shift: the key one fine bin below the window start
-    uint32_t hi, shift;
+    uint32_t hi, shift, sh2;
     bool active = true;
     __device__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
         const uint32_t lo = uniform(w.win_lo);
         shift = uniform(w.win_shift);
+        sh2 = shift - 2u;
         hi = lo + uniform(w.win_span);
         base = lo - (1u << shift);  // the window set-up keeps win_lo >= 2^shift
         active = uniform(w.win_ok) != 0;
@@ -2400,7 +2462,7 @@ struct WinPass1 {
         // the bins sit at LDS byte 0 (k_window checks it): the bin's byte
         // offset is its LDS address
         if (u <= hi) {
-            const uint32_t a = (__builtin_elementwise_sub_sat(u, base) >> shift) << 2;
+            const uint32_t a = (__builtin_elementwise_sub_sat(u, base) >> sh2) & ~3u;
             __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(size_t)a, 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -2522,11 +2584,7 @@ hipError_t launch_window_pass(hipStream_t st, const DevBufs& b, const WinBufs& w
 
 int window_blocks_per_cu(int pass, int variant, uint32_t block)
 {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, window_fn(pass, variant), (int)block, window_lds_bytes(pass)) !=
-        hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
+    return blocks_per_cu((const void*)window_fn(pass, variant), block, window_lds_bytes(pass));
 }
 
 // After window pass 1: per target, hit if its rank falls inside the window;

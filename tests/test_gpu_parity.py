@@ -460,7 +460,7 @@ def test_paper_rr_set_k99(ctx, system, m, tau, norm):
     assert np.array_equal(win["eps"], got["eps"]) and np.array_equal(win["det"], got["det"])
 
 
-@pytest.mark.parametrize("K", [21, 30, 31, 48, 49, 64])
+@pytest.mark.parametrize("K", [21, 39, 40, 41, 64, 65, 80])
 def test_path_switch_by_k(ctx, K):
     # the library switches between the range sweep and complete selection
     # plus the threshold sweep by K and selection method; every side of each
