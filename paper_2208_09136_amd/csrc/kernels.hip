@@ -34,6 +34,18 @@ namespace rqa {
 typedef const float __attribute__((address_space(1))) gf32;  // global
 typedef const float __attribute__((address_space(4))) cf32;  // constant: scalar loads for uniform indices
 
+// A wave-uniform value held in a vector register.  gfx950 issues 32-bit add,
+// sub, and, or, xor and right shifts at twice the rate of other VALU
+// instructions only when no operand is a scalar register (measured: an SGPR
+// source halves v_add_u32 and v_lshrrev_b32 to the rate of v_max_u32), so a
+// per-series shift or offset used once per cell is copied to a VGPR once.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t s)
+{
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -1033,6 +1045,28 @@ __device__ __forceinline__ uint32_t rho_of(uint32_t u, const RhoCtx& c)
     return r;
 }
 
+// rho_of for a table without multi-threshold buckets and a bucket shift of
+// at least 3, written with double-rate instructions: the bucket's byte offset
+// as a right shift by sh3 = shift - 3 (held in a VGPR) and a mask (the table
+// sits at LDS byte 0; the kernels check it), and the compare as the sign bit
+// of b - u (keys are at most 0x7F800000, an empty bucket's b is 0x7FFFFFFF:
+// the table is loaded with rho_table_entry).
+__device__ __forceinline__ uint32_t rho_fast(uint32_t u, const RhoCtx& c, uint32_t sh3)
+{
+    const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
+    const uint32_t off = (cl >> sh3) & ((RHO_TABLE - 1u) << 3);
+    const __attribute__((address_space(3))) uint32_t* e = (const __attribute__((address_space(3))) uint32_t*)(size_t)off;
+    return e[1] + ((e[0] - u) >> 31);
+}
+
+// A rank-table entry as the sweeps keep it in LDS: an empty bucket's first
+// threshold 0xFFFFFFFF becomes 0x7FFFFFFF, above every key either way.
+__device__ __forceinline__ uint2 rho_table_entry(uint2 e)
+{
+    e.x = min(e.x, 0x7FFFFFFFu);
+    return e;
+}
+
 // Range sweep: buckets of 2^shift bit patterns hold up to two boundaries
 // (x, y) and the rank base z (z + boundaries below the bucket); w > 0 marks a
 // bucket with w > 2 boundaries, compared one by one (rare).
@@ -1349,7 +1383,8 @@ struct RangeBody {
         if constexpr (kFast) {
             if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
                 // interior: every lane's diagonal covers [t0 - 1, t1 + WALK_SLACK]
-                const RangeCtx c = rc;
+                RangeCtx c = rc;
+                c.sh4 = in_vgpr(rc.sh4);
                 constexpr int HU = walk_block<NORM, MC, TW>();
                 if constexpr (LMC == 1) {
                     walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
@@ -1777,13 +1812,8 @@ struct HistBody {
     __device__ __forceinline__ void begin(uint32_t s)
     {
         const SeriesWork& w = works[s];
-        // an empty bucket's first threshold becomes 0x7FFFFFFF (above every
-        // key, and b - u cannot wrap): see rank()
-        for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x) {
-            uint2 e = rtab[(size_t)s * RHO_TABLE + i];
-            e.x = min(e.x, 0x7FFFFFFFu);
-            stab[i] = e;
-        }
+        for (uint32_t i = threadIdx.x; i < RHO_TABLE; i += blockDim.x)
+            stab[i] = rho_table_entry(rtab[(size_t)s * RHO_TABLE + i]);
         for (uint32_t i = threadIdx.x; i < RANK_MAX; i += blockDim.x) ses[i] = w.esorted[i];
         for (uint32_t i = threadIdx.x; i < HIST_SHORT * kcap; i += blockDim.x) dsh[i] = 0u;
         rc.table = stab;
@@ -1793,10 +1823,11 @@ struct HistBody {
         rc.shift = uniform(w.shift);
         rc.Kp = uniform(w.Kp);
         rc.z = 0;
-        // rank() needs a bucket shift of at least 3; narrower tables take the
-        // general lookup
+        // rho_fast needs a bucket shift of at least 3; narrower tables take
+        // the general lookup
         multi = uniform(w.multi) != 0 || rc.shift < 3u;
         sh3 = rc.shift - 3u;
+        sh3 = in_vgpr(sh3);
         active = uniform(w.nonfinite) == 0u;  // no ranks for a series with NaN or infinite samples
         dser = dglob + (size_t)s * hist_len * kcap;
         tbase = uniform(sds[s].chunk_begin) * chunk_tiles;
@@ -1831,21 +1862,12 @@ struct HistBody {
         nx = at(so - bd4);
         so = max(so - bd4, so1);
     }
-    // Rank of a key (at most Kp).  Without a multi-threshold bucket: the
-    // bucket's byte offset as a right shift and a mask (the table sits at LDS
-    // byte 0, k_hist checks it), and the compare as the sign bit of b - u
-    // (keys are at most 0x7F800000, an empty bucket's b is 0x7FFFFFFF).
+    // rank of a key (at most Kp)
     template <bool MULTI>
     __device__ __forceinline__ uint32_t rank(uint32_t u, const RhoCtx& c) const
     {
-        if constexpr (MULTI) {
-            return rho_of<true>(u, c);
-        } else {
-            const uint32_t cl = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(u), c.emin, c.emax));
-            const uint32_t off = (cl >> sh3) & ((RHO_TABLE - 1u) << 3);
-            const __attribute__((address_space(3))) uint32_t* e = (const __attribute__((address_space(3))) uint32_t*)(size_t)off;
-            return e[1] + ((e[0] - u) >> 31);
-        }
+        if constexpr (MULTI) return rho_of<true>(u, c);
+        else return rho_fast(u, c, sh3);
     }
     // cell of rank r <= Kp at position t
     __device__ __forceinline__ void cell(uint32_t r, uint32_t t)
@@ -2439,6 +2461,8 @@ struct WinPass1 {
         sh2 = shift - 2u;
         hi = lo + uniform(w.win_span);
         base = lo - (1u << shift);  // the window set-up keeps win_lo >= 2^shift
+        sh2 = in_vgpr(sh2);
+        base = in_vgpr(base);
         active = uniform(w.win_ok) != 0;
         for (uint32_t i = threadIdx.x; i <= WIN_BINS; i += blockDim.x) bins[i] = 0u;
     }
