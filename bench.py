@@ -70,7 +70,8 @@ def valu_roofline(ph, pairs, step_sec, probe, windowed):
     ph: phase -> device ms per step (HIP events on the library stream; one
     launch per phase); pairs: pairs per launch; probe: measured issue rates
     (lane-ops/s) of a double-rate (v_add_u32) and a half-rate (v_max_u32)
-    instruction.  `achieved` counts the algorithm's lower-bound VALU work
+    instruction, and of the add with a scalar-register operand, which gfx950
+    issues at the half rate.  `achieved` counts the algorithm's lower-bound VALU work
     (LOWER_BOUND_OPS) per launch over the launch time; measured instruction
     counts (SQ_INSTS_VALU x 64) come from the stored counter profile while
     it matches the device sources."""
@@ -86,6 +87,7 @@ def valu_roofline(ph, pairs, step_sec, probe, windowed):
             "algorithmic_ops_per_pair": LOWER_BOUND_OPS[names[dom]], "pairs_per_launch": pairs,
             "launch_ms": ph[dom], "measured_peak": probe["v_add_u32"] / 1e12,
             "measured_peak_half_rate": probe["v_max_u32"] / 1e12,
+            "measured_add_with_sgpr_operand": probe["v_add_u32_sgpr"] / 1e12 if "v_add_u32_sgpr" in probe else None,
             "survey_count_ratio": pairs * SURVEY_OPS_PER_PAIR / t / VALU_PEAK if names[dom] == "sweep" else None}
     step = {"algorithmic": sum(alg.values()) / step_sec / VALU_PEAK,
             "per_phase_algorithmic": {names[p]: alg[p] / (ph[p] * 1e-3) / VALU_PEAK for p in phases},
@@ -235,7 +237,7 @@ def main():
 
     # roofline of the dominant kernel (the phase with the largest device time;
     # one launch per phase per step) and the step's fraction of VALU peak
-    probe = {k: rqa.rqa_valu_rate(ctx.ctx, k)[0] for k in ("v_add_u32", "v_max_u32")}
+    probe = {k: rqa.rqa_valu_rate(ctx.ctx, k)[0] for k in ("v_add_u32", "v_max_u32", "v_add_u32_sgpr")}
     roofline, step_frac = valu_roofline(ph, sum(cells), sec, probe, windowed=windowed)
 
     # the same step with each selection method: identical results, different

@@ -217,7 +217,9 @@ int rqa_phase_times(rqa_ctx *ctx, double *times_out, int n_out);
  * Every lane of 8 workgroups of 256 threads per CU runs 16 independent
  * dependency chains of one instruction:
  *   kind 0: v_add_f32 (32-bit float add), 1: v_add_u32 (32-bit integer add),
- *   2: v_max_u32 (32-bit integer max).
+ *   2: v_max_u32 (32-bit integer max), 3: v_add_u32 with one operand in a
+ *   scalar register (gfx950 then issues it at the rate of kind 2).
+ * A kind outside 0..3 returns RQA_ERR_INVALID_ARG.
  * *lane_ops_per_s receives executed lane-operations per second of the
  * fastest of 8 timed launches (HIP events on the context stream);
  * *ms_out (or NULL) that launch's time.  Uses the context's scratch. */

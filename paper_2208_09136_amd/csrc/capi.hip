@@ -1368,7 +1368,7 @@ rqa_status rqa_valu_rate(rqa_ctx* c, uint32_t kind, double* lane_ops_per_s, doub
 {
     rqa_status st = check_ctx(c);
     if (st) return st;
-    if (kind > 2) return fail(RQA_ERR_INVALID_ARG, "probe kind %u outside 0..2", kind);
+    if (kind > 3) return fail(RQA_ERR_INVALID_ARG, "probe kind %u outside 0..3", kind);
     if (!lane_ops_per_s) return fail(RQA_ERR_INVALID_ARG, "lane_ops_per_s is NULL");
     // 32 waves per CU (8 per SIMD) with 16 independent chains each keep every
     // SIMD's issue port busy; 8 launches of a few milliseconds, the fastest counts

@@ -2206,59 +2206,64 @@ __global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict
 {
     __shared__ uint32_t es[RANK_MAX];
     __shared__ uint32_t sub[RQA_MAX_K];
-    __shared__ uint32_t s_kp, s_z, s_nsub, s_ok, s_shift;
+    // the per-target inputs and the group arrays in LDS: the serial part below
+    // then waits on no global load (each would cost a memory round trip)
+    __shared__ uint32_t s_addr[RQA_MAX_K], s_tsub[RQA_MAX_K], s_tgroup[RQA_MAX_K];
+    __shared__ uint32_t s_glo[RQA_MAX_K + 1], s_goff[RQA_MAX_K + 1];
+    __shared__ uint32_t s_kp, s_z, s_nsub, s_ok, s_shift, s_ng, s_miss;
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
     const uint32_t bits = window ? w.win_shift : (uint32_t)SEL_B3;
+    if (threadIdx.x == 0) s_miss = 0u;
+    __syncthreads();
+    // each target's range start and base count, loaded in parallel
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        if (window) {
+            if (!w.win_hit[r]) atomicOr(&s_miss, 1u);
+            s_addr[r] = w.win_lo + (w.win_fbin[r] << bits);
+            w.rbase[r] = w.win_base[r];
+        } else {
+            s_addr[r] = w.prefix[r] << SEL_B3;
+            w.rbase[r] = w.below[r];
+        }
+        sub[r] = s_addr[r];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         // series with a NaN or infinite sample end in an error; keep them out
         uint32_t ok = w.nonfinite ? 0u : 1u;
-        if (window) {
-            ok &= w.win_ok ? 1u : 0u;
-            for (uint32_t r = 0; r < K; ++r) ok &= w.win_hit[r] ? 1u : 0u;
-        }
+        if (window) ok &= (w.win_ok && !s_miss) ? 1u : 0u;
         s_ok = ok;
-        w.range_ok = ok;
-        w.range_bits = bits;
         if (ok) {
-            for (uint32_t r = 0; r < K; ++r) {
-                sub[r] = window ? w.win_lo + (w.win_fbin[r] << bits) : (w.prefix[r] << SEL_B3);
-                w.rbase[r] = window ? w.win_base[r] : w.below[r];
-            }
             const uint32_t ns = sort_unique(sub, K);
             s_nsub = ns;
-            w.nsub = ns;
-            for (uint32_t j = 0; j < ns; ++j) w.sub_lo[j] = sub[j];
-            for (uint32_t r = 0; r < K; ++r) {
-                const uint32_t a = window ? w.win_lo + (w.win_fbin[r] << bits) : (w.prefix[r] << SEL_B3);
-                w.t_sub[r] = index_of(sub, ns, a);
-            }
+            for (uint32_t r = 0; r < K; ++r) s_tsub[r] = index_of(sub, ns, s_addr[r]);
             // groups of adjacent ranges and their boundaries
             const uint64_t width = 1ull << bits;
             uint32_t ng = 0, kp = 0;
             for (uint32_t j = 0; j < ns; ++j) {
                 if (j == 0 || (uint64_t)sub[j] != (uint64_t)sub[j - 1] + width) {
-                    w.g_lo[ng] = sub[j];
-                    w.g_off[ng] = j << bits;
+                    s_glo[ng] = sub[j];
+                    s_goff[ng] = j << bits;
                     ++ng;
                 }
             }
-            w.ngroups = ng;
-            w.g_lo[ng] = 0;
-            w.g_off[ng] = 0;
+            s_ng = ng;
+            s_glo[ng] = 0;
+            s_goff[ng] = 0;
             for (uint32_t r = 0; r < K; ++r) {
-                const uint32_t j = w.t_sub[r];
+                const uint32_t j = s_tsub[r];
                 uint32_t gi = 0;
-                while (gi + 1 < ng && (w.g_off[gi + 1] >> bits) <= j) ++gi;
-                w.t_group[r] = gi;
+                while (gi + 1 < ng && (s_goff[gi + 1] >> bits) <= j) ++gi;
+                s_tgroup[r] = gi;
             }
-            const uint32_t z = w.g_lo[0] == 0 ? 1u : 0u;
+            const uint32_t z = s_glo[0] == 0 ? 1u : 0u;
             for (uint32_t gi = 0; gi < ng; ++gi) {
-                const uint32_t nj = (gi + 1 < ng ? (w.g_off[gi + 1] >> bits) : ns) - (w.g_off[gi] >> bits);
-                if (w.g_lo[gi] > 0) es[kp++] = w.g_lo[gi] - 1;
+                const uint32_t nj = (gi + 1 < ng ? (s_goff[gi + 1] >> bits) : ns) - (s_goff[gi] >> bits);
+                if (s_glo[gi] > 0) es[kp++] = s_glo[gi] - 1;
                 // last value of the group; keys never exceed +inf
-                const uint64_t last = (uint64_t)w.g_lo[gi] + ((uint64_t)nj << bits) - 1;
+                const uint64_t last = (uint64_t)s_glo[gi] + ((uint64_t)nj << bits) - 1;
                 es[kp++] = (uint32_t)(last < 0x7F800000ull ? last : 0x7F800000ull);
             }
             s_kp = kp;
@@ -2266,7 +2271,25 @@ __global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict
         }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        w.range_ok = s_ok;
+        w.range_bits = bits;
+        if (s_ok) {
+            w.nsub = s_nsub;
+            w.ngroups = s_ng;
+        }
+    }
     if (!s_ok) return;
+    // the group and target arrays back to the series' working state
+    for (uint32_t j = threadIdx.x; j < s_nsub; j += blockDim.x) w.sub_lo[j] = sub[j];
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+        w.t_sub[r] = s_tsub[r];
+        w.t_group[r] = s_tgroup[r];
+    }
+    for (uint32_t g = threadIdx.x; g <= s_ng; g += blockDim.x) {
+        w.g_lo[g] = s_glo[g];
+        w.g_off[g] = s_goff[g];
+    }
     // clear the fine counters of the ranges
     const uint32_t nfine = s_nsub << bits;
     uint64_t* fk = fineK + (size_t)s * fine_stride;
@@ -2613,12 +2636,14 @@ int window_blocks_per_cu(int pass, int variant, uint32_t block)
 
 // After window pass 1: per target, hit if its rank falls inside the window;
 // its fine bin and the count below that bin; pass-2 slots and table.
-__global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
-                                                      uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
-                                                      uint64_t* __restrict__ fine, uint32_t clear_fine)
+__global__ void __launch_bounds__(1024) k_window_scan1(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+                                                       uint64_t* __restrict__ bins, uint8_t* __restrict__ table,
+                                                       uint64_t* __restrict__ fine, uint32_t clear_fine)
 {
-    __shared__ uint64_t pre[257];
+    // up to 1024 threads (each then sums 39 of the 39,936 fine bins)
+    __shared__ uint64_t pre[1025];
     __shared__ uint32_t uniq[RQA_MAX_K];
+    __shared__ uint32_t s_hit[RQA_MAX_K], s_fbin[RQA_MAX_K];
     __shared__ uint32_t nuniq;
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
@@ -2634,9 +2659,13 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
         const uint64_t k = w.k[r];
         const bool hit = ok && k > below && k - below <= total;
         w.win_hit[r] = hit ? 1u : 0u;
+        s_hit[r] = hit ? 1u : 0u;
+        s_fbin[r] = 0u;
         if (hit) {
             uint64_t before;
-            w.win_fbin[r] = first_in_chunks(cb, WIN_BINS, pre, k - below, &before);
+            const uint32_t fb = first_in_chunks(cb, WIN_BINS, pre, k - below, &before);
+            w.win_fbin[r] = fb;
+            s_fbin[r] = fb;
             w.win_base[r] = below + before;
         }
     }
@@ -2644,13 +2673,13 @@ __global__ void __launch_bounds__(256) k_window_scan1(const SeriesDesc* __restri
     if (threadIdx.x == 0) {
         uint32_t n = 0;
         for (uint32_t r = 0; r < K; ++r)
-            if (w.win_hit[r]) uniq[n++] = w.win_fbin[r];
+            if (s_hit[r]) uniq[n++] = s_fbin[r];
         nuniq = sort_unique(uniq, n);
     }
     __syncthreads();
     const uint32_t nu = nuniq;
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x)
-        w.win_slot[r] = w.win_hit[r] ? index_of(uniq, nu, w.win_fbin[r]) : (uint32_t)NO_SLOT;
+        w.win_slot[r] = s_hit[r] ? index_of(uniq, nu, s_fbin[r]) : (uint32_t)NO_SLOT;
     __syncthreads();
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) tb[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.win_nslots = nu;
@@ -2696,7 +2725,9 @@ hipError_t launch_window_scan(hipStream_t st, const DevBufs& b, const WinBufs& w
     // scan 1 clears the fine counters of window pass 2 unless the range sweep
     // (which clears its own) follows
     if (pass == 1)
-        hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(256), 0, st, b.sd, b.work, w.bins, w.table, w.fine,
+        // few series: 1024 threads share each series' bins; many: 256, so
+        // that several series' workgroups share a CU
+        hipLaunchKernelGGL(k_window_scan1, dim3(b.S), dim3(b.S <= 128 ? 1024 : 256), 0, st, b.sd, b.work, w.bins, w.table, w.fine,
                            w.fine ? 1u : 0u);
     else hipLaunchKernelGGL(k_window_scan2, dim3(b.S, b.K), dim3(256), 0, st, b.sd, b.work, w.fine);
     return hipGetLastError();

@@ -19,13 +19,15 @@ constexpr int PROBE_UNROLL = 8;
 constexpr int PROBE_BLOCK = 256;
 
 // KIND 0: v_add_f32 (32-bit float add), KIND 1: v_add_u32 (32-bit integer
-// add), KIND 2: v_max_u32 (32-bit integer max).
+// add), KIND 2: v_max_u32 (32-bit integer max), KIND 3: v_add_u32 with a
+// scalar-register operand (which drops the add to the rate of KIND 2).
 template <int KIND>
-__device__ __forceinline__ void probe_op(uint32_t& x, uint32_t y)
+__device__ __forceinline__ void probe_op(uint32_t& x, uint32_t y, uint32_t ys)
 {
     if constexpr (KIND == 0) asm volatile("v_add_f32 %0, %1, %0" : "+v"(x) : "v"(y));
     else if constexpr (KIND == 1) asm volatile("v_add_u32 %0, %1, %0" : "+v"(x) : "v"(y));
-    else asm volatile("v_max_u32 %0, %1, %0" : "+v"(x) : "v"(y));
+    else if constexpr (KIND == 2) asm volatile("v_max_u32 %0, %1, %0" : "+v"(x) : "v"(y));
+    else asm volatile("v_add_u32 %0, %1, %0" : "+v"(x) : "s"(ys));
 }
 
 template <int KIND>
@@ -34,13 +36,14 @@ __global__ void __launch_bounds__(PROBE_BLOCK) k_valu_probe(uint32_t* __restrict
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t x[PROBE_CHAINS];
     const uint32_t y = seed ^ tid;
+    const uint32_t ys = seed;
 #pragma unroll
     for (int c = 0; c < PROBE_CHAINS; ++c) x[c] = tid * 2654435761u + (uint32_t)c;
     for (uint32_t it = 0; it < iters; ++it) {
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; ++u) {
 #pragma unroll
-            for (int c = 0; c < PROBE_CHAINS; ++c) probe_op<KIND>(x[c], y);
+            for (int c = 0; c < PROBE_CHAINS; ++c) probe_op<KIND>(x[c], y, ys);
         }
     }
     uint32_t acc = 0;
@@ -62,7 +65,8 @@ hipError_t launch_valu_probe(hipStream_t st, int kind, uint32_t blocks, uint32_t
     switch (kind) {
     case 0: hipLaunchKernelGGL(k_valu_probe<0>, dim3(blocks), dim3(PROBE_BLOCK), 0, st, out, iters, 0x9E3779B9u); break;
     case 1: hipLaunchKernelGGL(k_valu_probe<1>, dim3(blocks), dim3(PROBE_BLOCK), 0, st, out, iters, 0x9E3779B9u); break;
-    default: hipLaunchKernelGGL(k_valu_probe<2>, dim3(blocks), dim3(PROBE_BLOCK), 0, st, out, iters, 0x9E3779B9u); break;
+    case 2: hipLaunchKernelGGL(k_valu_probe<2>, dim3(blocks), dim3(PROBE_BLOCK), 0, st, out, iters, 0x9E3779B9u); break;
+    default: hipLaunchKernelGGL(k_valu_probe<3>, dim3(blocks), dim3(PROBE_BLOCK), 0, st, out, iters, 0x9E3779B9u); break;
     }
     return hipGetLastError();
 }

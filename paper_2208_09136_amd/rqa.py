@@ -159,7 +159,7 @@ def rqa_set_timing(ctx, enable=True):
     _check(load().rqa_set_timing(ctx, 1 if enable else 0))
 
 
-VALU_PROBES = {"v_add_f32": 0, "v_add_u32": 1, "v_max_u32": 2}
+VALU_PROBES = {"v_add_f32": 0, "v_add_u32": 1, "v_max_u32": 2, "v_add_u32_sgpr": 3}
 
 
 def rqa_valu_rate(ctx, kind):
