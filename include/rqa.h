@@ -266,6 +266,14 @@ rqa_status rqa_autotune_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev,
 rqa_status rqa_sketch_batch(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
                             const rqa_params *p, uint64_t seed, float *features_out, uint32_t *scale_out);
 
+/* The same sketch's sampled keys, sorted: sample_out (host, S *
+ * RQA_SKETCH_PAIRS) receives for series s the RQA_SKETCH_PAIRS key bit
+ * patterns of its sampled pairs in ascending order (the order statistics the
+ * sample window of RQA_SEL_SAMPLE is taken from; its median is scale_out of
+ * rqa_sketch_batch).  Arguments and errors as rqa_sketch_batch. */
+rqa_status rqa_sketch_sample(rqa_ctx *ctx, uint32_t S, const float *concat_dev, const uint64_t *offsets,
+                             const rqa_params *p, uint64_t seed, uint32_t *sample_out);
+
 /* Threshold-bracket network (an extension of the method; the paper has no
  * learned part): a perceptron 66 -> 128 -> 128 -> 20 with exact GELU hidden
  * layers mapping the sketch features to the offsets

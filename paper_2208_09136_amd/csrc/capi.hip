@@ -342,6 +342,8 @@ struct Job {
     std::vector<uint64_t> M;
     std::vector<float> features;     // S*SKETCH_FEATURES (sketch mode)
     std::vector<uint32_t> scale;     // S (sketch mode)
+    bool want_sample = false;        // sketch mode: also the sorted sample keys
+    std::vector<uint32_t> sample;    // S*SKETCH_P (want_sample)
     std::vector<uint8_t> hit;        // S*K, window selection: target resolved in the window
     uint32_t hist_len = 0;           // histogram mode: entries per row (length 0 .. hist_len-1)
     uint32_t hist_kp = 0;            // histogram mode: largest number of distinct thresholds
@@ -514,7 +516,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t o_rt = carve(sizeof(uint2) * S * RHO_TABLE);
     const bool sketch = (job.mode & MODE_SKETCH) || window;
     const size_t o_feat = sketch ? carve(sizeof(float) * S * SKETCH_FEATURES) : 0;
-    const size_t o_smp = window ? carve(sizeof(uint32_t) * S * SKETCH_P) : 0;
+    const bool keep_sample = window || ((job.mode & MODE_SKETCH) && job.want_sample);
+    const size_t o_smp = keep_sample ? carve(sizeof(uint32_t) * S * SKETCH_P) : 0;
     const size_t o_wtab = window ? carve((size_t)S * WIN_BINS) : 0;
     const size_t o_wfine = window && !fused ? carve(sizeof(uint64_t) * S * K * (1u << WIN_MAX_SHIFT)) : 0;
     // range sweep: fine counters of keys and line values, cleared by the set-up kernel
@@ -560,7 +563,8 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     const size_t hs_sd = sizeof(SeriesDesc) * S, hs_tgt = sizeof(uint64_t) * S * K;
     const size_t hs_res = sizeof(uint64_t) * S * res_words;
     const size_t hs_feat = (job.mode & MODE_SKETCH) ? sizeof(float) * S * SKETCH_FEATURES : 0;
-    const size_t hs_all = hs_sd + hs_tgt + hs_res + hs_feat + sizeof(float) * MLP_OUT;
+    const size_t hs_smp = ((job.mode & MODE_SKETCH) && job.want_sample) ? sizeof(uint32_t) * S * SKETCH_P : 0;
+    const size_t hs_all = hs_sd + hs_tgt + hs_res + hs_feat + sizeof(float) * MLP_OUT + hs_smp;
     char* hbase = nullptr;
     if (c->use_static) {
         // ordinary host memory (no pinned allocation); the copies below then
@@ -576,6 +580,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     uint64_t* h_res = (uint64_t*)(hbase + hs_sd + hs_tgt);
     float* h_feat = (float*)(hbase + hs_sd + hs_tgt + hs_res);
     float* h_delta = (float*)(hbase + hs_sd + hs_tgt + hs_res + hs_feat);
+    uint32_t* h_smp = (uint32_t*)(hbase + hs_sd + hs_tgt + hs_res + hs_feat + sizeof(float) * MLP_OUT);
     std::memcpy(h_delta, c->bracket_delta, sizeof(float) * MLP_OUT);
     if (window && job.sel == 1 && !c->has_model)
         return fail(RQA_ERR_INVALID_ARG, "RQA_SEL_LEARNED needs a network (rqa_mlp_init / rqa_mlp_set_params)");
@@ -596,7 +601,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     HIP_TRY(launch_zero(sm, pool + o_tick, zero_end - o_tick));
     HIP_TRY(launch_check_finite(sm, all, maxn, (const uint64_t*)(pool + o_tgt), as_rank));
     if (sketch)
-        HIP_TRY(launch_sketch(sm, all, (float*)(pool + o_feat), window ? (uint32_t*)(pool + o_smp) : nullptr));
+        HIP_TRY(launch_sketch(sm, all, (float*)(pool + o_feat), keep_sample ? (uint32_t*)(pool + o_smp) : nullptr));
     if (window) {
         HIP_TRY(hipMemcpyAsync(pool + o_delta, h_delta, sizeof(float) * MLP_OUT, hipMemcpyHostToDevice, sm));
         if (job.sel == 3) {
@@ -782,6 +787,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     HIP_TRY(launch_pack_results(sm, all, lines_out, (uint64_t*)(pool + o_res)));
     HIP_TRY(hipMemcpyAsync(h_res, pool + o_res, hs_res, hipMemcpyDeviceToHost, sm));
     if (hs_feat) HIP_TRY(hipMemcpyAsync(h_feat, pool + o_feat, hs_feat, hipMemcpyDeviceToHost, sm));
+    if (hs_smp) HIP_TRY(hipMemcpyAsync(h_smp, pool + o_smp, hs_smp, hipMemcpyDeviceToHost, sm));
     if (hist) {
         // rows straight into the caller's buffer, series back in caller order
         if (!job.hist_dst) return fail(RQA_ERR_INVALID_ARG, "histogram destination is NULL");
@@ -806,6 +812,7 @@ rqa_status run_job(rqa_ctx* c, Job& job)
     if (job.mode & MODE_SKETCH) {
         job.features.assign((size_t)S * SKETCH_FEATURES, 0.f);
         job.scale.assign(S, 0);
+        if (hs_smp) job.sample.assign((size_t)S * SKETCH_P, 0u);
     }
     if (window) job.hit.assign((size_t)S * K, 0);
     for (uint32_t i = 0; i < S; ++i) {
@@ -824,6 +831,9 @@ rqa_status run_job(rqa_ctx* c, Job& job)
         if (job.mode & MODE_SKETCH) {
             std::memcpy(&job.features[(size_t)s * SKETCH_FEATURES], h_feat + (size_t)i * SKETCH_FEATURES,
                         sizeof(float) * SKETCH_FEATURES);
+            if (hs_smp)
+                std::memcpy(&job.sample[(size_t)s * SKETCH_P], h_smp + (size_t)i * SKETCH_P,
+                            sizeof(uint32_t) * SKETCH_P);
             job.scale[s] = scale;
         }
         for (uint32_t r = 0; r < K; ++r) {
@@ -1591,6 +1601,37 @@ rqa_status rqa_autotune_batch(rqa_ctx* c, uint32_t S, const float* concat, const
     Job job;
     if ((st = build_batch_job(job, S, concat, offsets, p, rr, K))) return st;
     return tune_job(c, job, nullptr, chunk_tiles_out);
+}
+
+static rqa_status sketch_job(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,
+                             const rqa_params* p, uint64_t seed, bool want_sample, Job& job)
+{
+    rqa_status st;
+    job.base = concat;
+    job.K = 1;
+    job.mode = MODE_SKETCH;
+    job.seed = seed;
+    job.want_sample = want_sample;
+    for (uint32_t s = 0; s < S; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(RQA_ERR_INVALID_ARG, "offsets decrease at series %u", s);
+        uint64_t nv, M;
+        if ((st = check_params(&p[s], offsets[s + 1] - offsets[s], &nv, &M))) return st;
+        job.series.push_back({offsets[s], offsets[s + 1] - offsets[s], p[s]});
+    }
+    return run_job(c, job);
+}
+
+rqa_status rqa_sketch_sample(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,
+                             const rqa_params* p, uint64_t seed, uint32_t* sample_out)
+{
+    if (c) reset_phases(c);
+    rqa_status st = check_ctx(c);
+    if (st) return st;
+    if (S == 0 || !concat || !offsets || !p || !sample_out) return fail(RQA_ERR_INVALID_ARG, "a required pointer is NULL");
+    Job job;
+    if ((st = sketch_job(c, S, concat, offsets, p, seed, true, job))) return st;
+    std::memcpy(sample_out, job.sample.data(), sizeof(uint32_t) * job.sample.size());
+    return RQA_OK;
 }
 
 rqa_status rqa_sketch_batch(rqa_ctx* c, uint32_t S, const float* concat, const uint64_t* offsets,

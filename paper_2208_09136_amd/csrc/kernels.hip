@@ -2749,10 +2749,12 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t s)
 // SplitMix64, pair index v mod M in diagonal-major order), their keys sorted
 // in LDS, the median as scale, and the histogram of (bits - scale) >> 21
 // clamped to SKETCH_BINS quarter-binade bins.
-__global__ void __launch_bounds__(1024) k_sketch(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
+constexpr uint32_t SKETCH_THREADS = 1024;
+__global__ void __launch_bounds__(SKETCH_THREADS) k_sketch(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
                                                 float* __restrict__ features, uint32_t* __restrict__ sample_sorted)
 {
     __shared__ uint32_t keys[SKETCH_P];
+    __shared__ uint32_t keys2[SKETCH_P];
     __shared__ uint32_t hist[SKETCH_BINS];
     const uint32_t s = blockIdx.x;
     const SeriesDesc& sd = sds[s];
@@ -2777,20 +2779,59 @@ __global__ void __launch_bounds__(1024) k_sketch(const SeriesDesc* __restrict__ 
         keys[q] = __float_as_uint(key);
     }
     __syncthreads();
-    // bitonic sort of the sampled key bits, ascending
+    // bitonic sort of the sampled key bits, ascending.  Thread t holds
+    // elements 4t .. 4t+3 in registers: partners at distance 1 and 2 are in
+    // the same thread, at 4 .. 128 in another lane of the same wave
+    // (shuffles), and only the ten stages at 256 .. 2048 go through LDS (two
+    // buffers, one barrier each).
+    static_assert(SKETCH_P == 4 * SKETCH_THREADS, "four sample keys per thread");
+    const uint32_t t = threadIdx.x;
+    uint32_t x[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = keys[4 * t + c];
+    int cur = 0;
+    __syncthreads();
     for (uint32_t k = 2; k <= (uint32_t)SKETCH_P; k <<= 1) {
-        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-            for (uint32_t i = threadIdx.x; i < (uint32_t)SKETCH_P; i += blockDim.x) {
-                const uint32_t l = i ^ jj;
-                if (l > i) {
-                    const uint32_t a = keys[i], c = keys[l];
-                    const bool up = (i & k) == 0;
-                    if ((a > c) == up) { keys[i] = c; keys[l] = a; }
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 4 * 64) {
+                uint32_t* buf = cur ? keys2 : keys;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) buf[4 * t + c] = x[c];
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint32_t i = 4 * t + c, b = buf[i ^ j];
+                    const bool keep_min = ((i & k) == 0) == ((i & j) == 0);
+                    x[c] = keep_min ? min(x[c], b) : max(x[c], b);
+                }
+                cur ^= 1;
+            } else if (j >= 4) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint32_t i = 4 * t + c, b = (uint32_t)__shfl_xor((int)x[c], (int)(j >> 2));
+                    const bool keep_min = ((i & k) == 0) == ((i & j) == 0);
+                    x[c] = keep_min ? min(x[c], b) : max(x[c], b);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if ((c & (int)j) == 0) {
+                        const uint32_t i = 4 * t + c;
+                        const uint32_t a = x[c], b = x[c | (int)j];
+                        const bool up = (i & k) == 0;
+                        x[c] = up ? min(a, b) : max(a, b);
+                        x[c | (int)j] = up ? max(a, b) : min(a, b);
+                    }
                 }
             }
-            __syncthreads();
         }
     }
+    // the sorted keys back to LDS, once every thread has read its last
+    // partner there
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) keys[4 * t + c] = x[c];
+    __syncthreads();
     const uint32_t scale = keys[SKETCH_P / 2 - 1];
     for (uint32_t q = threadIdx.x; q < (uint32_t)SKETCH_P; q += blockDim.x) {
         int idx = (int)(((int64_t)keys[q] - (int64_t)scale) >> 21) + SKETCH_BINS / 2;
@@ -2811,7 +2852,7 @@ __global__ void __launch_bounds__(1024) k_sketch(const SeriesDesc* __restrict__ 
 hipError_t launch_sketch(hipStream_t st, const DevBufs& b, float* features, uint32_t* sample_sorted)
 {
     // 1024 threads: four sample keys per thread through the 78 bitonic stages
-    hipLaunchKernelGGL(k_sketch, dim3(b.S), dim3(1024), 0, st, b.sd, b.work, features, sample_sorted);
+    hipLaunchKernelGGL(k_sketch, dim3(b.S), dim3(SKETCH_THREADS), 0, st, b.sd, b.work, features, sample_sorted);
     return hipGetLastError();
 }
 

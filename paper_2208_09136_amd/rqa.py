@@ -67,6 +67,7 @@ SIGNATURES = {
     "rqa_autotune": (_i32, [_vp, _vp, _u64, _pp, _dp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "rqa_autotune_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _dp, _u32, ctypes.POINTER(_u32)]),
     "rqa_sketch_batch": (_i32, [_vp, _u32, _vp, _up, _pp, _u64, _fp, ctypes.POINTER(_u32)]),
+    "rqa_sketch_sample": (_i32, [_vp, _u32, _vp, _up, _pp, _u64, ctypes.POINTER(_u32)]),
     "rqa_mlp_init": (_i32, [_vp, _u64]),
     "rqa_mlp_set_params": (_i32, [_vp, _fp, _u64]),
     "rqa_mlp_get_params": (_i32, [_vp, _fp, _u64]),
@@ -222,6 +223,21 @@ def rqa_sketch_batch(ctx, concat, offsets, params, seed):
     _check(load().rqa_sketch_batch(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, int(seed),
                                    _p(feats, ctypes.c_float), scale.ctypes.data_as(ctypes.POINTER(_u32))))
     return feats, scale
+
+
+SKETCH_PAIRS = 4096
+
+
+def rqa_sketch_sample(ctx, concat, offsets, params, seed):
+    """Sorted sampled key bit patterns (S, 4096) uint32 of the sketch of S series."""
+    ptr, _ = _series_ptr(concat)
+    offs = _a(offsets, np.uint64)
+    S = len(offs) - 1
+    prm = (rqa_params * S)(*[_params(p) for p in params])
+    out = np.zeros((S, SKETCH_PAIRS), np.uint32)
+    _check(load().rqa_sketch_sample(ctx, S, ptr, _p(offs, ctypes.c_uint64), prm, int(seed),
+                                    out.ctypes.data_as(ctypes.POINTER(_u32))))
+    return out
 
 
 MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 66, 20, 27668
@@ -509,6 +525,9 @@ class Context:
 
     def sketch_batch(self, concat, offsets, params, seed):
         return rqa_sketch_batch(self.ctx, concat, offsets, params, seed)
+
+    def sketch_sample(self, concat, offsets, params, seed):
+        return rqa_sketch_sample(self.ctx, concat, offsets, params, seed)
 
     def mlp_init(self, seed):
         rqa_mlp_init(self.ctx, seed)

@@ -416,6 +416,22 @@ def test_sketch_matches_oracle(ctx):
         assert np.array_equal(feats[s], f)
 
 
+def test_sketch_sample_sorted_equals_oracle(ctx):
+    # the sample the sample window takes its order statistics from: every
+    # sampled key, sorted, bit for bit the oracle's (ties included)
+    from oracle import sketch
+    cases = [synth.config_small(0), synth.config_medium(n=2000)[12], synth.config_medium(n=3000)[3],
+             {"y": np.round(synth.series("logistic", 1500, 5.0, (3, 1, 2, 3)), 1).astype(np.float32),
+              "m": 1, "tau": 1, "norm": 0, "theiler": 1, "lmin": 2}]
+    ys = [c["y"] for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(y) for y in ys])]).astype(np.uint64)
+    got = ctx.sketch_sample(dev(np.concatenate(ys)), offs, [prm(c) for c in cases], seed=4242)
+    for s, c in enumerate(cases):
+        keys = sketch.sample_keys(c["y"], c["m"], c["tau"], c["norm"], c["theiler"], 4242 + s)
+        want = np.sort(np.asarray(keys, np.float32).view(np.uint32))
+        assert np.array_equal(got[s], want), s
+
+
 @pytest.mark.parametrize("m,tau,norm,w,lmin", [
     (1, 1, 0, 1, 2), (3, 5, 1, 1, 2), (3, 3, 0, 2, 2), (2, 3, 1, 1, 2), (3, 5, 1, 1, 3),
     (1, 1, 1, 1, 7), (3, 5, 0, 5, 16), (1, 1, 0, 1, 1)])
