@@ -266,6 +266,21 @@ __device__ __forceinline__ void walk(const float* y, int d, int x0, int count, F
 template <int NORM, int M, int TAU>
 constexpr int walk_block() { return Walker<NORM, M, TAU>::HU; }
 
+// End of the part of a tile the walker can take: the whole tile when every
+// lane's diagonal covers [t0, t1 + WALK_SLACK] (interior tiles), else the
+// longest prefix [t0, tw) whose cells and slack every lane of the band owns,
+// in whole pairs of half-blocks (so that state a body carries from block to
+// block is exact at tw); the cells after tw take the per-cell path.  A band
+// with fewer than 64 diagonals has no walker part.
+template <int HU>
+__device__ __forceinline__ int walk_end(const TileGeo& g)
+{
+    if (g.t1 + TILE_W + WALK_SLACK <= g.len0) return g.t1;
+    const int safe = g.len0 - TILE_W - WALK_SLACK;
+    if (safe <= g.t0) return g.t0;
+    return g.t0 + ((safe - g.t0) / (2 * HU)) * (2 * HU);
+}
+
 // ------------------------------------------------------------------ zero / checks
 
 __global__ void k_zero(uint32_t* p, size_t words)
@@ -428,12 +443,14 @@ __device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t ti
 {
     const TileGeo g = tile_geo(sd, tile_id, lane);
     constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
+    int tx = g.t0;  // cells before tx are counted by the walker
     if constexpr (kFast) {
         constexpr int TW = MC == 1 ? 1 : TC;
         constexpr int HU = walk_block<NORM, MC, TW>();
-        if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
-            // interior: every lane's diagonal covers [t0, t1 + WALK_SLACK]
-            walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+        const int tw = walk_end<HU>(g);
+        if (tw > g.t0) {
+            // every lane's diagonal covers [t0, tw + WALK_SLACK]
+            walk<NORM, MC, TW>(sd.y, g.d, g.t0, tw - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                 uint32_t lk[HU];
 #pragma unroll
                 for (int u = 0; u < HU; ++u) lk[u] = body.look(k[u]);
@@ -441,10 +458,10 @@ __device__ __forceinline__ void select_tile(const SeriesScalars& sd, uint32_t ti
                 for (int u = 0; u < HU; ++u)
                     if (u < valid) body.count(k[u], lk[u]);
             });
-            return;
+            tx = tw;
         }
     }
-    for (int x = g.t0; x < g.t1; ++x) {
+    for (int x = tx; x < g.t1; ++x) {
         if (x < g.len) {
             const uint32_t u = __float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau));
             body.count(u, body.look(u));
@@ -1179,13 +1196,21 @@ struct SweepBody {
         const TileGeo g = tile_geo(sd, tile_id, lane);
         constexpr bool kFast = (LMC == 1 || LMC == 2) && MC > 0 && (MC == 1 || TC > 0);
         constexpr int TW = MC == 1 ? 1 : TC;
+        int tx = g.t0;  // cells before tx are counted by the walker
+        // lmin = 2: ranks of the cells before and at the next one counted
+        uint32_t rm1 = 0, r0 = 0;
+        if constexpr (LMC == 2) {
+            rm1 = rho_at<MULTI>(sd, g, g.t0 - 1);
+            r0 = rho_at<MULTI>(sd, g, g.t0);
+        }
         if constexpr (kFast) {
-            if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
-                // interior: every lane's diagonal covers [t0 - 1, t1 + WALK_SLACK]
+            constexpr int HU = walk_block<NORM, MC, TW>();
+            const int tw = walk_end<HU>(g);
+            if (tw > g.t0) {
+                // every lane's diagonal covers [t0 - 1, tw + WALK_SLACK]
                 const RhoCtx c = rc;
-                constexpr int HU = walk_block<NORM, MC, TW>();
                 if constexpr (LMC == 1) {
-                    walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0, tw - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                         uint32_t r[HU];
 #pragma unroll
                         for (int u = 0; u < HU; ++u) r[u] = rho_of<MULTI>(k[u], c);
@@ -1194,9 +1219,7 @@ struct SweepBody {
                             if (u < valid) emit(r[u], r[u], lane);
                     });
                 } else {
-                    uint32_t rm1 = rho_at<MULTI>(sd, g, g.t0 - 1);
-                    uint32_t r0 = rho_at<MULTI>(sd, g, g.t0);
-                    walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, tw - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                         uint32_t r[HU];
 #pragma unroll
                         for (int u = 0; u < HU; ++u) r[u] = rho_of<MULTI>(k[u], c);
@@ -1210,18 +1233,16 @@ struct SweepBody {
                         }
                     });
                 }
-                return;
+                tx = tw;
             }
         }
         if constexpr (LMC == 1) {
-            for (int x = g.t0; x < g.t1; ++x) {
+            for (int x = tx; x < g.t1; ++x) {
                 const uint32_t r = rho_at<MULTI>(sd, g, x);
                 emit(r, r, lane);
             }
         } else if constexpr (LMC == 2) {
-            uint32_t rm1 = rho_at<MULTI>(sd, g, g.t0 - 1);
-            uint32_t r0 = rho_at<MULTI>(sd, g, g.t0);
-            for (int x = g.t0; x < g.t1; ++x) {
+            for (int x = tx; x < g.t1; ++x) {
                 const uint32_t rp1 = rho_at<MULTI>(sd, g, x + 1);
                 emit(r0, max(r0, min(rm1, rp1)), lane);
                 rm1 = r0;
@@ -1380,14 +1401,24 @@ struct RangeBody {
         const TileGeo g = tile_geo(sd, tile_id, lane);
         constexpr bool kFast = (LMC == 1 || LMC == 2) && MC > 0 && (MC == 1 || TC > 0);
         constexpr int TW = MC == 1 ? 1 : TC;
+        int tx = g.t0;  // cells before tx are counted by the walker
+        // lmin = 2: keys and ranks of the cells before and at the next one counted
+        uint32_t km1 = 0, k0 = 0, rm1 = 0, r0 = 0;
+        if constexpr (LMC == 2) {
+            km1 = key_at(sd, g, g.t0 - 1);
+            k0 = key_at(sd, g, g.t0);
+            rm1 = rank_at<MULTI>(km1);
+            r0 = rank_at<MULTI>(k0);
+        }
         if constexpr (kFast) {
-            if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
-                // interior: every lane's diagonal covers [t0 - 1, t1 + WALK_SLACK]
+            constexpr int HU = walk_block<NORM, MC, TW>();
+            const int tw = walk_end<HU>(g);
+            if (tw > g.t0) {
+                // every lane's diagonal covers [t0 - 1, tw + WALK_SLACK]
                 RangeCtx c = rc;
                 c.sh4 = in_vgpr(rc.sh4);
-                constexpr int HU = walk_block<NORM, MC, TW>();
                 if constexpr (LMC == 1) {
-                    walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0, tw - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                         uint32_t r[HU];
                         uint32_t acc = 0;
 #pragma unroll
@@ -1404,9 +1435,7 @@ struct RangeBody {
                 } else {
                     // the walk runs one cell ahead: block keys are the right
                     // neighbours of the cells counted in the block
-                    uint32_t km1 = key_at(sd, g, g.t0 - 1), k0 = key_at(sd, g, g.t0);
-                    uint32_t rm1 = rank_at<MULTI>(km1), r0 = rank_at<MULTI>(k0);
-                    walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                    walk<NORM, MC, TW>(sd.y, g.d, g.t0 + 1, tw - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                         uint32_t r[HU];
                         // a line value is one of the ranks of its cell and the two
                         // neighbours, so an odd rank among those of the block and the
@@ -1443,26 +1472,25 @@ struct RangeBody {
                                 }
                             }
                         }
-                        // state for the next block (only full blocks have one)
+                        // state for the next block (the walk covers whole blocks
+                        // only, so after it: the keys and ranks at tw - 1 and tw)
                         km1 = k[HU - 2];
                         k0 = k[HU - 1];
                         rm1 = r[HU - 2];
                         r0 = r[HU - 1];
                     });
                 }
-                return;
+                tx = tw;
             }
         }
         if constexpr (LMC == 1) {
-            for (int x = g.t0; x < g.t1; ++x) {
+            for (int x = tx; x < g.t1; ++x) {
                 const uint32_t k = key_at(sd, g, x);
                 const uint32_t r = rank_at<MULTI>(k);
                 if (__ballot(r & 1u)) fine(dk, r, k);
             }
         } else if constexpr (LMC == 2) {
-            uint32_t km1 = key_at(sd, g, g.t0 - 1), k0 = key_at(sd, g, g.t0);
-            uint32_t rm1 = rank_at<MULTI>(km1), r0 = rank_at<MULTI>(k0);
-            for (int x = g.t0; x < g.t1; ++x) {
+            for (int x = tx; x < g.t1; ++x) {
                 const uint32_t kp1 = key_at(sd, g, x + 1);
                 const uint32_t rp1 = rank_at<MULTI>(kp1);
                 const uint32_t lam = max(r0, min(rm1, rp1));
@@ -1918,15 +1946,16 @@ struct HistBody {
         at(so0) = top;
         pm = 0;
         constexpr bool kFast = MC > 0 && (MC == 1 || TC > 0);
-        bool done = false;
+        int tx = g.t0;  // cells before tx are taken by the walker
         if constexpr (kFast) {
             constexpr int TW = MC == 1 ? 1 : TC;
             constexpr int HU = walk_block<NORM, MC, TW>();
-            if (g.t1 + TILE_W + WALK_SLACK <= g.len0) {
-                // interior: every lane's diagonal covers [t0, t1 + WALK_SLACK]
+            const int tw = walk_end<HU>(g);
+            if (tw > g.t0) {
+                // every lane's diagonal covers [t0, tw + WALK_SLACK]
                 const RhoCtx c = rc;
                 uint32_t t = t0;
-                walk<NORM, MC, TW>(sd.y, g.d, g.t0, g.t1 - g.t0, [&](const uint32_t(&k)[HU], int valid) {
+                walk<NORM, MC, TW>(sd.y, g.d, g.t0, tw - g.t0, [&](const uint32_t(&k)[HU], int valid) {
                     uint32_t rk[HU];
 #pragma unroll
                     for (int u = 0; u < HU; ++u) rk[u] = rank<MULTI>(k[u], c);
@@ -1935,11 +1964,11 @@ struct HistBody {
                         if (u < valid) cell(rk[u], t + (uint32_t)u);
                     t += HU;
                 });
-                done = true;
+                tx = tw;
             }
         }
-        if (!done) {
-            for (int x = g.t0; x < g.t1; ++x) {
+        {
+            for (int x = tx; x < g.t1; ++x) {
                 uint32_t r = Kp;
                 if (x < g.len)
                     r = min(rho_of<MULTI>(__float_as_uint(pair_key<NORM, MC, TC>(sd.y, x, x + g.d, sd.m, sd.tau)), rc),
