@@ -825,23 +825,44 @@ __device__ void block_cumsum(const uint64_t* __restrict__ src, uint64_t* cum, ui
     __syncthreads();
 }
 
-// Prefix sums of n u64 counts, one chunk of ceil(n / blockDim.x) per thread:
-// pre[t] = sum of the chunks before thread t's, pre[blockDim.x] = the total.
-// Then first_in_chunks finds, for one count kk <= total, the first index
-// whose inclusive prefix reaches kk (binary search over the chunk prefixes,
-// then a walk of one chunk), with the sum before it.
+// Prefix sums of n u64 counts in blockDim.x contiguous chunks of
+// ceil(n / blockDim.x): pre[t] = sum of the chunks before chunk t,
+// pre[blockDim.x] = the total.  Short chunks are summed by their thread;
+// long ones (more than 16 counts) by the thread's wave, wave w taking chunks
+// 64 w .. 64 w + 63 with coalesced loads of 64 consecutive counts and a wave
+// reduction, so that no lane walks a long chunk alone.  Then
+// first_in_chunks finds, for one count kk <= total, the first index whose
+// inclusive prefix reaches kk.
 __device__ void chunk_prefix(const uint64_t* __restrict__ c, uint32_t n, uint64_t* pre /* LDS [blockDim.x + 1] */)
 {
     const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
-    const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
-    uint64_t sum = 0;
-    for (uint32_t i = b0; i < b1; ++i) sum += c[i];
+    const uint32_t lane = threadIdx.x & 63, wbase = threadIdx.x & ~63u;
+    uint64_t mine = 0;
+    if (per <= 16) {
+        const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
+        for (uint32_t i = b0; i < b1; ++i) mine += c[i];
+    } else {
+#pragma unroll 4
+        for (uint32_t q = 0; q < 64; ++q) {
+            const uint32_t b0 = min((wbase + q) * per, n), b1 = min(b0 + per, n);
+            uint64_t sum = 0;
+            for (uint32_t i = b0 + lane; i < b1; i += 64) sum += c[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            if (lane == q) mine = sum;
+        }
+    }
     uint64_t tot;
-    pre[threadIdx.x] = block_excl_scan(sum, &tot);
+    pre[threadIdx.x] = block_excl_scan(mine, &tot);
     if (threadIdx.x == 0) pre[blockDim.x] = tot;
     __syncthreads();
 }
 
+// Called by all 64 lanes of one wave with the same arguments (every lane
+// gets the result): the first index i with pre-sum + c[..i] >= kk, found by
+// a binary search over the chunk prefixes and a wave scan of 64 counts at a
+// time through the chunk; the chunk's last index if none reaches kk.
+// *before = the sum of the counts below the index.
 __device__ uint32_t first_in_chunks(const uint64_t* __restrict__ c, uint32_t n, const uint64_t* pre, uint64_t kk,
                                     uint64_t* before)
 {
@@ -852,14 +873,27 @@ __device__ uint32_t first_in_chunks(const uint64_t* __restrict__ c, uint32_t n, 
         if (pre[mid] < kk) lo = mid; else hi = mid;
     }
     uint64_t run = pre[lo];
-    const uint32_t b1 = min(lo * per + per, n);
-    uint32_t i = lo * per;
-    for (; i + 1 < b1; ++i) {
-        if (run + c[i] >= kk) break;
-        run += c[i];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t b0 = lo * per, b1 = min(b0 + per, n);
+    for (uint32_t base = b0; base < b1; base += 64) {
+        const uint32_t i = base + lane;
+        const uint64_t v = i < b1 ? c[i] : 0;
+        uint64_t x = v;  // inclusive prefix over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(x, off);
+            if (lane >= (uint32_t)off) x += y;
+        }
+        const unsigned long long hit = __ballot(i < b1 && (run + x >= kk || i + 1 == b1));
+        if (hit) {
+            const int l = __ffsll(hit) - 1;
+            *before = run + __shfl(x, l) - __shfl(v, l);
+            return base + (uint32_t)l;
+        }
+        run += __shfl(x, 63);
     }
     *before = run;
-    return i;
+    return b0;
 }
 
 // First index i in [0, n) with cum[i] >= k (cum inclusive, nondecreasing);
@@ -967,10 +1001,15 @@ __device__ void target_bin(const uint64_t* __restrict__ h, uint32_t n, uint64_t 
                            uint64_t* pre, uint32_t* c, uint64_t* run)
 {
     chunk_prefix(h, n, pre);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // wave 0
         if (pre[blockDim.x] >= want) {
-            *c = first_in_chunks(h, n, pre, want, run);
-        } else {
+            uint64_t r;
+            const uint32_t i = first_in_chunks(h, n, pre, want, &r);
+            if (threadIdx.x == 0) {
+                *c = i;
+                *run = r;
+            }
+        } else if (threadIdx.x == 0) {
             *c = n - 1;
             *run = pre[blockDim.x];
             atomicOr(&w.status, flag);
@@ -2365,12 +2404,15 @@ __global__ void __launch_bounds__(256) k_range_scan(const SeriesDesc* __restrict
     // the target's fine bin: first c with rbase + keys up to bin c >= k
     const uint64_t want = w.k[r] - w.rbase[r];
     chunk_prefix(fk + fj, width, pre);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // wave 0
         if (pre[blockDim.x] >= want) {
             uint64_t before;
-            s_c = first_in_chunks(fk + fj, width, pre, want, &before);
-            s_run = before;
-        } else {
+            const uint32_t i = first_in_chunks(fk + fj, width, pre, want, &before);
+            if (threadIdx.x == 0) {
+                s_c = i;
+                s_run = before;
+            }
+        } else if (threadIdx.x == 0) {
             s_c = width - 1;
             s_run = pre[blockDim.x];
             atomicOr(&w.status, 32u);
@@ -2684,18 +2726,21 @@ __global__ void __launch_bounds__(1024) k_window_scan1(const SeriesDesc* __restr
     const uint64_t* cb = bins + (size_t)s * WIN_BINS;
     chunk_prefix(cb, WIN_BINS, pre);
     const uint64_t total = pre[blockDim.x];
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
+    // one wave per target
+    for (uint32_t r = threadIdx.x >> 6; r < K; r += blockDim.x >> 6) {
         const uint64_t k = w.k[r];
         const bool hit = ok && k > below && k - below <= total;
-        w.win_hit[r] = hit ? 1u : 0u;
-        s_hit[r] = hit ? 1u : 0u;
-        s_fbin[r] = 0u;
-        if (hit) {
-            uint64_t before;
-            const uint32_t fb = first_in_chunks(cb, WIN_BINS, pre, k - below, &before);
-            w.win_fbin[r] = fb;
+        uint32_t fb = 0;
+        uint64_t before = 0;
+        if (hit) fb = first_in_chunks(cb, WIN_BINS, pre, k - below, &before);
+        if ((threadIdx.x & 63) == 0) {
+            w.win_hit[r] = hit ? 1u : 0u;
+            s_hit[r] = hit ? 1u : 0u;
             s_fbin[r] = fb;
-            w.win_base[r] = below + before;
+            if (hit) {
+                w.win_fbin[r] = fb;
+                w.win_base[r] = below + before;
+            }
         }
     }
     __syncthreads();
@@ -2736,13 +2781,15 @@ __global__ void __launch_bounds__(256) k_window_scan2(const SeriesDesc* __restri
     const uint64_t* c = fine + ((size_t)s * K + w.win_slot[r]) * (1u << WIN_MAX_SHIFT);
     const uint64_t want = w.k[r] - w.win_base[r];
     chunk_prefix(c, nsub, pre);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // wave 0
         if (pre[blockDim.x] >= want) {
             uint64_t before;
             const uint32_t idx = first_in_chunks(c, nsub, pre, want, &before);
-            w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + idx;
-            w.count[r] = w.win_base[r] + before + c[idx];
-        } else {
+            if (threadIdx.x == 0) {
+                w.eps_bits[r] = w.win_lo + (w.win_fbin[r] << w.win_shift) + idx;
+                w.count[r] = w.win_base[r] + before + c[idx];
+            }
+        } else if (threadIdx.x == 0) {
             w.win_hit[r] = 0u;
             atomicOr(&w.status, 8u);
         }
