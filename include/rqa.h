@@ -236,9 +236,11 @@ rqa_status rqa_set_timing(rqa_ctx *ctx, int enable);
 rqa_status rqa_set_shape(rqa_ctx *ctx, uint32_t segment, uint32_t chunk_tiles);
 
 /* Launch-shape autotuner (batched persistent launch of the workload
- * configurations).  Times the whole path (rqa_run) on the given series for
- * candidate segment lengths (powers of two from 64 to 4096) and chunk sizes
- * {2, 8, 32, 128, 512}, and records the fastest in the context's table under the size
+ * configurations).  Times the whole path (rqa_run with default flags, so
+ * with the selection method such a call takes) on the given series, as the
+ * device time of its phases (the fastest of three runs after one untimed
+ * run), for candidate segment lengths (powers of two from 64 to 4096) and
+ * chunk sizes {2, 8, 32, 128, 512}, and records the fastest in the context's table under the size
  * bucket (log2 of the number of vectors, norm, embedding and line class, K up
  * to 32 or beyond).  segment_out/chunk_tiles_out (or NULL) receive it.
  * Arguments as in rqa_run. */
