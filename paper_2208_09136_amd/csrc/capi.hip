@@ -1242,12 +1242,21 @@ rqa_status tune_job(rqa_ctx* c, Job& job, uint32_t* seg_out, uint32_t* chunk_out
         double best = 1e300;
         Job whole = job;
         whole.mode = mode;
+        // the largest chunk within 3% of the fastest: shorter chunks cost
+        // per-chunk set-up that some paths feel much more than the one tuned
+        // (plain selection's pass 2 at 2 tiles per chunk: twice the time)
+        double ms_of[sizeof(CHUNK_CANDIDATES) / sizeof(CHUNK_CANDIDATES[0])];
+        int n = 0;
         for (uint32_t CT : CHUNK_CANDIDATES) {
             c->chunk_tiles = CT;
             double ms;
             if ((st = time_job(c, whole, 3, &ms))) break;
-            if (ms < best) { best = ms; best_chunk = CT; }
+            ms_of[n++] = ms;
+            best = std::min(best, ms);
         }
+        if (!st)
+            for (int i = 0; i < n; ++i)
+                if (ms_of[i] <= best * 1.03) best_chunk = CHUNK_CANDIDATES[i];
     }
     c->seg = save_seg;
     c->chunk_tiles = save_chunk;
