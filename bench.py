@@ -44,12 +44,13 @@ K = 20
 # one-op lane slots per clock x 2.4 GHz.  The library's issue-rate probe
 # measures what the chip sustains (rqa_valu_rate) and is reported beside it.
 VALU_PEAK = 157.3e12 / 2
-# Survey count of the method's work: about 2 + key/K VALU ops per pair and
-# threshold (a compare and a run update per threshold, the key shared) --
+# Work of a per-threshold implementation of the method: about 2 + key/K VALU
+# ops per pair and threshold (a compare and a run update per threshold, the
+# key shared) --
 # 48 per pair at K = 20 with the Euclidean m = 3 key (8 ops).  The range
 # sweep does O(1) work per pair whatever K is, so this count over time is a
 # ratio to peak, not a fraction of it.
-SURVEY_OPS_PER_PAIR = 2 * K + 8
+PER_THRESHOLD_OPS_PER_PAIR = 2 * K + 8
 # Lower bound of this algorithm's VALU work per pair (lane-ops), per kernel,
 # Euclidean m = 3: the key needs one new difference, its square and m - 1 = 2
 # adds per cell (the walker reuses each difference m times), 4 ops; then
@@ -88,7 +89,7 @@ def valu_roofline(ph, pairs, step_sec, probe, windowed):
             "launch_ms": ph[dom], "measured_peak": probe["v_add_u32"] / 1e12,
             "measured_peak_half_rate": probe["v_max_u32"] / 1e12,
             "measured_add_with_sgpr_operand": probe["v_add_u32_sgpr"] / 1e12 if "v_add_u32_sgpr" in probe else None,
-            "survey_count_ratio": pairs * SURVEY_OPS_PER_PAIR / t / VALU_PEAK if names[dom] == "sweep" else None}
+            "per_threshold_count_ratio": pairs * PER_THRESHOLD_OPS_PER_PAIR / t / VALU_PEAK if names[dom] == "sweep" else None}
     step = {"algorithmic": sum(alg.values()) / step_sec / VALU_PEAK,
             "per_phase_algorithmic": {names[p]: alg[p] / (ph[p] * 1e-3) / VALU_PEAK for p in phases},
             "issue": None, "per_phase_issue": None}
