@@ -908,29 +908,35 @@ __device__ __forceinline__ uint32_t first_reaching(const uint64_t* cum, uint32_t
     return lo;
 }
 
-// Sort v[0..n) ascending and drop repeats; returns the distinct count.
-__device__ uint32_t sort_unique(uint32_t* v, uint32_t n)
+// The distinct values of v[0..n) in ascending order, written to out[] (which
+// must not overlap v), over the entries with keep[i] != 0 (all entries when
+// keep is null); pos[i] = the position of v[i] among them, for kept entries.
+// flag is LDS scratch of n words.  One entry per thread, in parallel (a
+// serial sort on one thread waits on an LDS round trip per step), so n is at
+// most RQA_MAX_K and every caller runs at least that many threads.  Called by
+// the whole block; synchronises it.  Returns the number of distinct values.
+static_assert(RQA_MAX_K <= 256, "the set-up kernels give every target a thread of 256");
+__device__ uint32_t block_sort_unique(const uint32_t* v, const uint32_t* keep, uint32_t n, uint32_t* out,
+                                      uint32_t* pos, uint32_t* flag)
 {
-    for (uint32_t i = 1; i < n; ++i) {
-        const uint32_t x = v[i];
-        uint32_t j = i;
-        while (j > 0 && v[j - 1] > x) { v[j] = v[j - 1]; --j; }
-        v[j] = x;
+    const uint32_t i = threadIdx.x;
+    const bool mine = i < n && (keep == nullptr || keep[i] != 0u);
+    const uint32_t x = mine ? v[i] : 0u;
+    // the first kept entry of each value stands for it
+    bool first = mine;
+    if (mine)
+        for (uint32_t j = 0; j < i; ++j)
+            if ((keep == nullptr || keep[j] != 0u) && v[j] == x) first = false;
+    if (i < n) flag[i] = first ? 1u : 0u;
+    const uint32_t nu = (uint32_t)__syncthreads_count(first);
+    if (mine) {
+        uint32_t p = 0;
+        for (uint32_t j = 0; j < n; ++j) p += (flag[j] != 0u && v[j] < x) ? 1u : 0u;
+        pos[i] = p;
+        if (first) out[p] = x;
     }
-    uint32_t u = 0;
-    for (uint32_t i = 0; i < n; ++i)
-        if (u == 0 || v[i] != v[u - 1]) v[u++] = v[i];
-    return u;
-}
-
-__device__ __forceinline__ uint32_t index_of(const uint32_t* v, uint32_t n, uint32_t x)
-{
-    uint32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (v[mid] <= x) lo = mid; else hi = mid;
-    }
-    return lo;
+    __syncthreads();
+    return nu;
 }
 
 // After pass 1: locate each target's bucket, assign pass-2 slots, fill T1.
@@ -938,8 +944,7 @@ __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sd
                                                uint8_t* __restrict__ T1, const uint64_t* __restrict__ h1)
 {
     __shared__ uint64_t cum[SEL_N1];
-    __shared__ uint32_t uniq[RQA_MAX_K];
-    __shared__ uint32_t nuniq;
+    __shared__ uint32_t s_pre[RQA_MAX_K], uniq[RQA_MAX_K], s_pos[RQA_MAX_K], s_flag[RQA_MAX_K];
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
@@ -950,15 +955,13 @@ __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sd
         if (cum[b] < k) atomicOr(&w.status, 1u);
         w.prefix[r] = b;
         w.below[r] = b ? cum[b - 1] : 0;
-        uniq[r] = b;
+        s_pre[r] = b;
     }
     uint8_t* t1 = T1 + (size_t)s * SEL_N1;
     for (uint32_t i = threadIdx.x; i < SEL_N1; i += blockDim.x) t1[i] = NO_SLOT;
     __syncthreads();
-    if (threadIdx.x == 0) nuniq = sort_unique(uniq, K);
-    __syncthreads();
-    const uint32_t nu = nuniq;
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
+    const uint32_t nu = block_sort_unique(s_pre, nullptr, K, uniq, s_pos, s_flag);
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = s_pos[r];
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) t1[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.nslots2 = nu;
 }
@@ -968,8 +971,7 @@ __global__ void __launch_bounds__(256) k_scan1(const SeriesDesc* __restrict__ sd
 __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works,
                                                uint8_t* __restrict__ T2, const uint64_t* __restrict__ h2all)
 {
-    __shared__ uint32_t uniq[RQA_MAX_K];
-    __shared__ uint32_t nuniq;
+    __shared__ uint32_t s_pre[RQA_MAX_K], uniq[RQA_MAX_K], s_pos[RQA_MAX_K], s_flag[RQA_MAX_K];
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
@@ -979,17 +981,13 @@ __global__ void __launch_bounds__(256) k_scan2(const SeriesDesc* __restrict__ sd
     (void)h2;
     for (uint32_t i = threadIdx.x; i < n2 * SEL_N2; i += blockDim.x) t2[i] = NO_SLOT;
     // below / prefix of every target come from k_scan2_find
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) uniq[r] = w.prefix[r];
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) s_pre[r] = w.prefix[r];
     __syncthreads();
-    if (threadIdx.x == 0) nuniq = sort_unique(uniq, K);
+    const uint32_t nu = block_sort_unique(s_pre, nullptr, K, uniq, s_pos, s_flag);
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x)
+        t2[w.slot[r] * SEL_N2 + (s_pre[r] & (SEL_N2 - 1))] = (uint8_t)s_pos[r];
     __syncthreads();
-    const uint32_t nu = nuniq;
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
-        const uint32_t u = index_of(uniq, nu, w.prefix[r]);
-        t2[w.slot[r] * SEL_N2 + (w.prefix[r] & (SEL_N2 - 1))] = (uint8_t)u;
-    }
-    __syncthreads();
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = index_of(uniq, nu, w.prefix[r]);
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.slot[r] = s_pos[r];
     if (threadIdx.x == 0) w.nslots3 = nu;
 }
 
@@ -1791,17 +1789,15 @@ __device__ void build_rank_table(SeriesWork& w, const uint32_t* es, uint32_t kp,
 __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict__ sds,
                                                     SeriesWork* __restrict__ works, uint2* __restrict__ rtab)
 {
-    __shared__ uint32_t es[RQA_MAX_K];
-    __shared__ uint32_t s_kp, s_shift;
+    __shared__ uint32_t s_eps[RQA_MAX_K], es[RQA_MAX_K], s_pos[RQA_MAX_K], s_flag[RQA_MAX_K];
+    __shared__ uint32_t s_shift;
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) es[r] = w.eps_bits[r];
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) s_eps[r] = w.eps_bits[r];
     __syncthreads();
-    if (threadIdx.x == 0) s_kp = sort_unique(es, K);
-    __syncthreads();
-    const uint32_t kp = s_kp;
-    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.dmap[r] = index_of(es, kp, w.eps_bits[r]);
+    const uint32_t kp = block_sort_unique(s_eps, nullptr, K, es, s_pos, s_flag);
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) w.dmap[r] = s_pos[r];
     build_rank_table(w, es, kp, 0u, rtab + (size_t)s * RHO_TABLE, &s_shift);
 }
 
@@ -2274,11 +2270,13 @@ __global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict
 {
     __shared__ uint32_t es[RANK_MAX];
     __shared__ uint32_t sub[RQA_MAX_K];
-    // the per-target inputs and the group arrays in LDS: the serial part below
-    // then waits on no global load (each would cost a memory round trip)
+    // the per-target inputs and the group arrays in LDS, worked on by one
+    // thread per target or range (serially, each step would wait on a round
+    // trip to memory or LDS)
     __shared__ uint32_t s_addr[RQA_MAX_K], s_tsub[RQA_MAX_K], s_tgroup[RQA_MAX_K];
+    __shared__ uint32_t s_flag[RQA_MAX_K], s_gid[RQA_MAX_K];
     __shared__ uint32_t s_glo[RQA_MAX_K + 1], s_goff[RQA_MAX_K + 1];
-    __shared__ uint32_t s_kp, s_z, s_nsub, s_ok, s_shift, s_ng, s_miss;
+    __shared__ uint32_t s_kp, s_z, s_shift, s_miss;
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
@@ -2295,71 +2293,74 @@ __global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict
             s_addr[r] = w.prefix[r] << SEL_B3;
             w.rbase[r] = w.below[r];
         }
-        sub[r] = s_addr[r];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // series with a NaN or infinite sample end in an error; keep them out
-        uint32_t ok = w.nonfinite ? 0u : 1u;
-        if (window) ok &= (w.win_ok && !s_miss) ? 1u : 0u;
-        s_ok = ok;
-        if (ok) {
-            const uint32_t ns = sort_unique(sub, K);
-            s_nsub = ns;
-            for (uint32_t r = 0; r < K; ++r) s_tsub[r] = index_of(sub, ns, s_addr[r]);
-            // groups of adjacent ranges and their boundaries
-            const uint64_t width = 1ull << bits;
-            uint32_t ng = 0, kp = 0;
-            for (uint32_t j = 0; j < ns; ++j) {
-                if (j == 0 || (uint64_t)sub[j] != (uint64_t)sub[j - 1] + width) {
-                    s_glo[ng] = sub[j];
-                    s_goff[ng] = j << bits;
-                    ++ng;
-                }
+    // series with a NaN or infinite sample end in an error; keep them out
+    // (the same value on every thread)
+    const bool ok = w.nonfinite == 0u && (!window || (w.win_ok != 0u && s_miss == 0u));
+    uint32_t ns = 0, ng = 0;
+    if (ok) {
+        ns = block_sort_unique(s_addr, nullptr, K, sub, s_tsub, s_flag);
+        // groups of adjacent ranges: a range starts a group unless it follows
+        // the one before it directly
+        const uint64_t width = 1ull << bits;
+        const uint32_t j = threadIdx.x;
+        const bool start = j < ns && (j == 0 || (uint64_t)sub[j] != (uint64_t)sub[j - 1] + width);
+        if (j < ns) s_flag[j] = start ? 1u : 0u;
+        ng = (uint32_t)__syncthreads_count(start);
+        if (j < ns) {
+            uint32_t gi = 0;  // starts after the first one, up to j
+            for (uint32_t i = 1; i <= j; ++i) gi += s_flag[i];
+            s_gid[j] = gi;
+            if (start) {
+                s_glo[gi] = sub[j];
+                s_goff[gi] = j << bits;
             }
-            s_ng = ng;
+        }
+        __syncthreads();
+        if (j < K) s_tgroup[j] = s_gid[s_tsub[j]];
+        // the rank table's boundaries, per group: its first value - 1 (unless
+        // that value is 0, which only the first group can start at) and its
+        // last value, in group order
+        const uint32_t z = s_glo[0] == 0u ? 1u : 0u;
+        if (j < ng) {
+            const uint32_t glo = s_glo[j];
+            const uint32_t nj = (j + 1 < ng ? (s_goff[j + 1] >> bits) : ns) - (s_goff[j] >> bits);
+            // keys never exceed +inf
+            const uint64_t last = (uint64_t)glo + ((uint64_t)nj << bits) - 1;
+            const uint32_t at = j == 0 ? 0u : 2u * j - z;
+            if (glo > 0u) es[at] = glo - 1u;
+            es[at + (glo > 0u ? 1u : 0u)] = (uint32_t)(last < 0x7F800000ull ? last : 0x7F800000ull);
+        }
+        if (j == 0) {
             s_glo[ng] = 0;
             s_goff[ng] = 0;
-            for (uint32_t r = 0; r < K; ++r) {
-                const uint32_t j = s_tsub[r];
-                uint32_t gi = 0;
-                while (gi + 1 < ng && (s_goff[gi + 1] >> bits) <= j) ++gi;
-                s_tgroup[r] = gi;
-            }
-            const uint32_t z = s_glo[0] == 0 ? 1u : 0u;
-            for (uint32_t gi = 0; gi < ng; ++gi) {
-                const uint32_t nj = (gi + 1 < ng ? (s_goff[gi + 1] >> bits) : ns) - (s_goff[gi] >> bits);
-                if (s_glo[gi] > 0) es[kp++] = s_glo[gi] - 1;
-                // last value of the group; keys never exceed +inf
-                const uint64_t last = (uint64_t)s_glo[gi] + ((uint64_t)nj << bits) - 1;
-                es[kp++] = (uint32_t)(last < 0x7F800000ull ? last : 0x7F800000ull);
-            }
-            s_kp = kp;
+            s_kp = 2u * ng - z;
             s_z = z;
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        w.range_ok = s_ok;
+        w.range_ok = ok ? 1u : 0u;
         w.range_bits = bits;
-        if (s_ok) {
-            w.nsub = s_nsub;
-            w.ngroups = s_ng;
+        if (ok) {
+            w.nsub = ns;
+            w.ngroups = ng;
         }
     }
-    if (!s_ok) return;
+    if (!ok) return;
     // the group and target arrays back to the series' working state
-    for (uint32_t j = threadIdx.x; j < s_nsub; j += blockDim.x) w.sub_lo[j] = sub[j];
+    for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) w.sub_lo[j] = sub[j];
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) {
         w.t_sub[r] = s_tsub[r];
         w.t_group[r] = s_tgroup[r];
     }
-    for (uint32_t g = threadIdx.x; g <= s_ng; g += blockDim.x) {
+    for (uint32_t g = threadIdx.x; g <= ng; g += blockDim.x) {
         w.g_lo[g] = s_glo[g];
         w.g_off[g] = s_goff[g];
     }
     // clear the fine counters of the ranges
-    const uint32_t nfine = s_nsub << bits;
+    const uint32_t nfine = ns << bits;
     uint64_t* fk = fineK + (size_t)s * fine_stride;
     uint64_t* fl = fineL + (size_t)s * fine_stride;
     for (uint32_t i = threadIdx.x; i < nfine; i += blockDim.x) {
@@ -2713,9 +2714,8 @@ __global__ void __launch_bounds__(1024) k_window_scan1(const SeriesDesc* __restr
 {
     // up to 1024 threads (each then sums 39 of the 39,936 fine bins)
     __shared__ uint64_t pre[1025];
-    __shared__ uint32_t uniq[RQA_MAX_K];
+    __shared__ uint32_t uniq[RQA_MAX_K], s_pos[RQA_MAX_K], s_flag[RQA_MAX_K];
     __shared__ uint32_t s_hit[RQA_MAX_K], s_fbin[RQA_MAX_K];
-    __shared__ uint32_t nuniq;
     const uint32_t s = blockIdx.x;
     const uint32_t K = sds[s].K;
     SeriesWork& w = works[s];
@@ -2744,16 +2744,9 @@ __global__ void __launch_bounds__(1024) k_window_scan1(const SeriesDesc* __restr
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t n = 0;
-        for (uint32_t r = 0; r < K; ++r)
-            if (s_hit[r]) uniq[n++] = s_fbin[r];
-        nuniq = sort_unique(uniq, n);
-    }
-    __syncthreads();
-    const uint32_t nu = nuniq;
+    const uint32_t nu = block_sort_unique(s_fbin, s_hit, K, uniq, s_pos, s_flag);
     for (uint32_t r = threadIdx.x; r < K; r += blockDim.x)
-        w.win_slot[r] = s_hit[r] ? index_of(uniq, nu, s_fbin[r]) : (uint32_t)NO_SLOT;
+        w.win_slot[r] = s_hit[r] ? s_pos[r] : (uint32_t)NO_SLOT;
     __syncthreads();
     for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) tb[uniq[u]] = (uint8_t)u;
     if (threadIdx.x == 0) w.win_nslots = nu;
