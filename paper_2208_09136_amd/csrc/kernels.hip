@@ -1738,6 +1738,18 @@ int sweep_blocks_per_cu(int variant, bool ranges, uint32_t block, size_t lds)
     return blocks_per_cu(ranges ? (const void*)range_fn(variant) : (const void*)sweep_fn(variant), block, lds);
 }
 
+// Number of entries of the ascending array es[0..n) below x (a binary
+// search: the table builders below look up both edges of every bucket).
+__device__ __forceinline__ uint32_t count_below(const uint32_t* es, uint32_t n, uint64_t x)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)es[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 // Rank table of one series over the ascending thresholds es[0..kp) with rank
 // base z: spans the buckets (key >> shift) from es[0] to es[kp-1] with the
 // smallest shift that fits RHO_TABLE buckets; bucket a (mod RHO_TABLE) stores
@@ -1771,11 +1783,7 @@ __device__ void build_rank_table(SeriesWork& w, const uint32_t* es, uint32_t kp,
         uint2 e = make_uint2(0xFFFFFFFFu, z);
         if (a <= a1) {
             const uint64_t lo = (uint64_t)a << sh, hi = (uint64_t)(a + 1) << sh;
-            uint32_t below = 0, inside = 0;
-            for (uint32_t i = 0; i < kp; ++i) {
-                below += (uint64_t)es[i] < lo;
-                inside += ((uint64_t)es[i] >= lo) && ((uint64_t)es[i] < hi);
-            }
+            const uint32_t below = count_below(es, kp, lo), inside = count_below(es, kp, hi) - below;
             e.x = inside ? es[below] : 0xFFFFFFFFu;
             e.y = (inside >= 2) ? ((z + below) | (inside << 16)) : z + below;
             if (inside >= 2) w.multi = 1u;
@@ -2240,11 +2248,7 @@ __device__ void build_range_table(SeriesWork& w, const uint32_t* es, uint32_t kp
         uint4 e = make_uint4(0x7FFFFFFFu, 0x7FFFFFFFu, z, 0u);
         if (a <= a1) {
             const uint64_t lo = (uint64_t)a << sh, hi = (uint64_t)(a + 1) << sh;
-            uint32_t below = 0, inside = 0;
-            for (uint32_t i = 0; i < kp; ++i) {
-                below += (uint64_t)es[i] < lo;
-                inside += ((uint64_t)es[i] >= lo) && ((uint64_t)es[i] < hi);
-            }
+            const uint32_t below = count_below(es, kp, lo), inside = count_below(es, kp, hi) - below;
             e.x = inside >= 1 ? es[below] : 0x7FFFFFFFu;
             e.y = inside >= 2 ? es[below + 1] : 0x7FFFFFFFu;
             e.z = z + below;
