@@ -825,12 +825,36 @@ __device__ void block_cumsum(const uint64_t* __restrict__ src, uint64_t* cum, ui
     __syncthreads();
 }
 
+// A u64 moved between lanes by a DPP control (row_mask and bank_mask all
+// rows and banks).
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum of a u64 over each aligned group of eight lanes, every lane of the
+// group getting it: lane ^ 1 and lane ^ 2 (quad permutations), then the
+// other half of the eight (row half mirror: lane i takes lane 7 - i).  DPP
+// moves read the neighbouring lanes' registers directly, with no LDS round
+// trip.  Called with the whole wave active.
+__device__ __forceinline__ uint64_t sum8_lanes(uint64_t x)
+{
+    x += dpp_u64<0xB1>(x);
+    x += dpp_u64<0x4E>(x);
+    x += dpp_u64<0x141>(x);
+    return x;
+}
+
 // Prefix sums of n u64 counts in blockDim.x contiguous chunks of
 // ceil(n / blockDim.x): pre[t] = sum of the chunks before chunk t,
 // pre[blockDim.x] = the total.  Short chunks are summed by their thread;
-// long ones (more than 16 counts) by the thread's wave, wave w taking chunks
-// 64 w .. 64 w + 63 with coalesced loads of 64 consecutive counts and a wave
-// reduction, so that no lane walks a long chunk alone.  Then
+// long ones (more than 16 counts) by eight lanes of the thread's wave, wave
+// w taking chunks 64 w .. 64 w + 63 eight at a time (each load then reads
+// eight runs of eight consecutive counts), so that no lane walks a long
+// chunk alone and the eight partial sums meet through DPP moves.  Then
 // first_in_chunks finds, for one count kk <= total, the first index whose
 // inclusive prefix reaches kk.
 __device__ void chunk_prefix(const uint64_t* __restrict__ c, uint32_t n, uint64_t* pre /* LDS [blockDim.x + 1] */)
@@ -842,15 +866,28 @@ __device__ void chunk_prefix(const uint64_t* __restrict__ c, uint32_t n, uint64_
         const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
         for (uint32_t i = b0; i < b1; ++i) mine += c[i];
     } else {
-#pragma unroll 4
-        for (uint32_t q = 0; q < 64; ++q) {
-            const uint32_t b0 = min((wbase + q) * per, n), b1 = min(b0 + per, n);
-            uint64_t sum = 0;
-            for (uint32_t i = b0 + lane; i < b1; i += 64) sum += c[i];
+        // lanes 8 g .. 8 g + 7 sum chunk wbase + 8 i + g in part[i]
+        const uint32_t g = lane >> 3, j = lane & 7;
+        const uint32_t nk = (per + 7) / 8;
+        uint64_t part[8];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-            if (lane == q) mine = sum;
+        for (uint32_t i = 0; i < 8; ++i) part[i] = 0;
+        for (uint32_t k = 0; k < nk; ++k) {
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) {
+                const uint32_t b0 = min((wbase + 8 * i + g) * per, n), b1 = min(b0 + per, n);
+                const uint32_t e = b0 + 8 * k + j;
+                part[i] += e < b1 ? c[e] : 0ull;
+            }
         }
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+            const uint64_t v = sum8_lanes(part[i]);
+            if (j == 0) pre[wbase + 8 * i + g] = v;
+        }
+        // per is the same on every thread, so is this branch
+        __syncthreads();
+        mine = pre[threadIdx.x];
     }
     uint64_t tot;
     pre[threadIdx.x] = block_excl_scan(mine, &tot);
