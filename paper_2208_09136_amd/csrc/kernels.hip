@@ -1775,6 +1775,10 @@ int sweep_blocks_per_cu(int variant, bool ranges, uint32_t block, size_t lds)
     return blocks_per_cu(ranges ? (const void*)range_fn(variant) : (const void*)sweep_fn(variant), block, lds);
 }
 
+// Threads of the sweeps' set-up kernels: each looks up a few table buckets
+// (binary searches whose steps wait on LDS), so more threads finish sooner.
+constexpr uint32_t PREP_THREADS = 1024;
+
 // Number of entries of the ascending array es[0..n) below x (a binary
 // search: the table builders below look up both edges of every bucket).
 __device__ __forceinline__ uint32_t count_below(const uint32_t* es, uint32_t n, uint64_t x)
@@ -1831,7 +1835,7 @@ __device__ void build_rank_table(SeriesWork& w, const uint32_t* es, uint32_t kp,
 
 // Sweep at given thresholds: per series the distinct sorted thresholds, the
 // caller->distinct map and the rank table.
-__global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict__ sds,
+__global__ void __launch_bounds__(PREP_THREADS) k_sweep_prep(const SeriesDesc* __restrict__ sds,
                                                     SeriesWork* __restrict__ works, uint2* __restrict__ rtab)
 {
     __shared__ uint32_t s_eps[RQA_MAX_K], es[RQA_MAX_K], s_pos[RQA_MAX_K], s_flag[RQA_MAX_K];
@@ -1848,7 +1852,7 @@ __global__ void __launch_bounds__(256) k_sweep_prep(const SeriesDesc* __restrict
 
 hipError_t launch_sweep_prep(hipStream_t st, const DevBufs& b)
 {
-    hipLaunchKernelGGL(k_sweep_prep, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.rtab);
+    hipLaunchKernelGGL(k_sweep_prep, dim3(b.S), dim3(PREP_THREADS), 0, st, b.sd, b.work, b.rtab);
     return hipGetLastError();
 }
 
@@ -2304,7 +2308,7 @@ __device__ void build_range_table(SeriesWork& w, const uint32_t* es, uint32_t kp
 // Distinct ranges are sorted, adjacent ones merge into groups, and the
 // group boundaries (first value - 1, last value) form the rank table; the
 // fine counters of the ranges are cleared.
-__global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict__ sds,
+__global__ void __launch_bounds__(PREP_THREADS) k_range_prep(const SeriesDesc* __restrict__ sds,
                                                     SeriesWork* __restrict__ works, uint2* __restrict__ rtab,
                                                     uint64_t* __restrict__ fineK, uint64_t* __restrict__ fineL,
                                                     uint32_t fine_stride, uint32_t window)
@@ -2413,7 +2417,7 @@ __global__ void __launch_bounds__(256) k_range_prep(const SeriesDesc* __restrict
 
 hipError_t launch_range_prep(hipStream_t st, const DevBufs& b, bool window)
 {
-    hipLaunchKernelGGL(k_range_prep, dim3(b.S), dim3(256), 0, st, b.sd, b.work, b.rtab, b.fineK, b.fineL,
+    hipLaunchKernelGGL(k_range_prep, dim3(b.S), dim3(PREP_THREADS), 0, st, b.sd, b.work, b.rtab, b.fineK, b.fineL,
                        b.fine_stride, window ? 1u : 0u);
     return hipGetLastError();
 }
