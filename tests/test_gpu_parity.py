@@ -496,3 +496,33 @@ def test_path_switch_by_k(ctx, K):
         win = ctx.run(dev(y), prm(case), rr, flags=flags)
         for key in ("eps", "count", "rr", "det", "det_mean"):
             assert np.array_equal(win[key], got[key]), (flags, key)
+
+
+def test_maximum_k(ctx):
+    # the largest target count a call takes, unsorted, with repeated rates and
+    # both extremes, in one call and in a batch of two series, with plain and
+    # sample-window selection: the scan and set-up kernels sort and number
+    # the targets one thread each, here at their largest size
+    from paper_2208_09136_amd import rqa
+    K = rqa.RQA_MAX_K
+    rng = np.random.default_rng(128)
+    extra = [0.05, 0.05, 0.3, 0.3, 1e-9, 1.0, 0.002, 0.7]
+    rr = rng.permutation(np.concatenate([np.linspace(0.002, 0.7, K - len(extra)), extra]))
+    assert len(rr) == K
+    cases = [{"name": f"maxk_{name}", "y": synth.series(name, n, 5.0, (21, i, 0, 0)), "m": 3, "tau": 5,
+              "norm": 1, "theiler": 1, "lmin": 2, "rr": rr}
+             for i, (name, n) in enumerate([("lorenz", 2000), ("logistic", 1500)])]
+    wants = [oracle_run(c) for c in cases]
+    offs = np.concatenate([[0], np.cumsum([len(c["y"]) for c in cases])]).astype(np.uint64)
+    concat = dev(np.concatenate([c["y"] for c in cases]))
+    for flags in (rqa.RQA_SEL_PLAIN, rqa.RQA_SEL_SAMPLE):
+        print(f"[parity] maxk K={K} flags={flags}", flush=True)
+        assert_run_equal(ctx.run(dev(cases[0]["y"]), prm(cases[0]), rr, flags=flags), wants[0], f"single {flags}")
+        out = ctx.batch(concat, offs, [prm(c) for c in cases], np.stack([rr, rr]), flags=flags)
+        for s, want in enumerate(wants):
+            label = f"batch {flags} series {s}"
+            assert np.array_equal(out["eps"][s].view(np.uint32), want["eps"].view(np.uint32)), label
+            assert np.array_equal(out["count"][s], want["count"]), label
+            assert np.array_equal(out["rr"][s], want["rr"]), label
+            assert np.array_equal(out["det"][s], want["det"], equal_nan=True), label
+            assert out["det_mean"][s] == want["det_mean"] or np.isnan(want["det_mean"]), label
