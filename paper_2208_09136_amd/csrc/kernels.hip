@@ -2561,23 +2561,33 @@ __global__ void k_window_from_offsets(const SeriesDesc* __restrict__ sds, Series
 
 // Window from the sorted sketch sample: for each target rate q = k/M, the
 // sample keys at ranks q P -/+ z sqrt(P q (1 - q)) (one more below), over
-// all targets.
-__global__ void k_window_from_sample(const SeriesDesc* __restrict__ sds, SeriesWork* __restrict__ works, uint32_t S,
-                                     const uint32_t* __restrict__ sample, float z)
+// all targets.  One wave per series, a lane per target (each lane's loads
+// depend on its target's count, so one thread walking the targets would wait
+// on two memory round trips per target); the bounds meet in a wave min / max.
+__global__ void __launch_bounds__(64) k_window_from_sample(const SeriesDesc* __restrict__ sds,
+                                                           SeriesWork* __restrict__ works, uint32_t S,
+                                                           const uint32_t* __restrict__ sample, float z)
 {
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+    const uint32_t s = blockIdx.x;
+    if (s >= S) return;  // uniform over the wave
     SeriesWork& w = works[s];
     const uint32_t* smp = sample + (size_t)s * SKETCH_P;
-    int64_t lo = 0x7F800000ll, hi = 0;
-    for (uint32_t r = 0; r < sds[s].K; ++r) {
-        const double q = (double)w.k[r] / (double)sds[s].M;
+    const uint32_t K = sds[s].K;
+    const double M = (double)sds[s].M;
+    long long lo = 0x7F800000ll, hi = 0;
+    for (uint32_t r = threadIdx.x; r < K; r += 64) {
+        const double q = (double)w.k[r] / M;
         const double c = q * SKETCH_P, sd = sqrt(SKETCH_P * q * (1.0 - q)) * z;
         const int ilo = (int)floor(c - sd) - 1, ihi = (int)ceil(c + sd);
-        lo = min(lo, ilo < 0 ? (int64_t)0 : (int64_t)smp[ilo]);
-        hi = max(hi, ihi >= SKETCH_P ? (int64_t)0x7F800000ll : (int64_t)smp[ihi]);
+        lo = min(lo, ilo < 0 ? 0ll : (long long)smp[ilo]);
+        hi = max(hi, ihi >= (int)SKETCH_P ? 0x7F800000ll : (long long)smp[ihi]);
     }
-    set_window(w, lo, hi, true);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+    }
+    if (threadIdx.x == 0) set_window(w, lo, hi, true);
 }
 
 // A window given by the caller, the same for every series.
@@ -2603,7 +2613,7 @@ hipError_t launch_window_from_offsets(hipStream_t st, const DevBufs& b, const fl
 hipError_t launch_window_from_sample(hipStream_t st, const DevBufs& b, const uint32_t* sample_sorted, const double*,
                                      float z)
 {
-    hipLaunchKernelGGL(k_window_from_sample, dim3((b.S + 63) / 64), dim3(64), 0, st, b.sd, b.work, b.S, sample_sorted, z);
+    hipLaunchKernelGGL(k_window_from_sample, dim3(b.S), dim3(64), 0, st, b.sd, b.work, b.S, sample_sorted, z);
     return hipGetLastError();
 }
 
